@@ -1,0 +1,269 @@
+/*
+ * n3p.h -- C ABI of libn3p: Newton's method in three precisions on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: C. T. Kelley, "Newton's Method in Three Precisions" (arXiv
+ * 2307.16051).  The nonlinear residual is evaluated in FP64, the Jacobian is
+ * stored in FP32, a half-precision copy of it is LU-factored, and the Newton
+ * step is computed by iterative refinement (IR) or GMRES-IR that reuse that
+ * factorisation (Algorithm 2.1 in Section 2; IR and GMRES-IR in Section 2.2).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are column-major: element (i, j) is at a[i + j*ld], ld >= n.
+ *   - Pointers documented as "device" must point to device memory of the
+ *     current HIP device; "host" pointers to host memory.  The library never
+ *     takes ownership of caller memory.
+ *   - The library never allocates device memory.  Entry points that need
+ *     scratch take a caller-provided workspace (device pointer + byte size);
+ *     the matching *_workspace_size function gives the minimum size.  A
+ *     workspace is owned by one call at a time: concurrent calls must use
+ *     different workspaces.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is enqueued on it.  Entry points that return results
+ *     to host memory (reports, info codes) synchronise the stream before
+ *     returning; the others are asynchronous.
+ *   - Pivot vectors are 0-based LAPACK-style interchange lists: at step k
+ *     row k was swapped with row ipiv[k] (ipiv[k] >= k).
+ *   - No C++ exception crosses this boundary; every entry point returns an
+ *     n3p_status (0 on success).
+ */
+#ifndef N3P_H
+#define N3P_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(_WIN32)
+#define N3P_API
+#else
+#define N3P_API __attribute__((visibility("default")))
+#endif
+
+/* ------------------------------------------------------------------ status */
+typedef enum n3p_status {
+    N3P_OK = 0,
+    N3P_NOT_CONVERGED = 1,  /* maxit reached; x holds the last iterate */
+    N3P_E_INVALID = -1,     /* bad argument (size, pointer, enum, option) */
+    N3P_E_NOMEM = -2,       /* workspace smaller than *_workspace_size */
+    N3P_E_SINGULAR = -3,    /* an exactly zero pivot (info > 0) */
+    N3P_E_NONFINITE = -4,   /* Inf/NaN in F, J or the factors after the scaling retry */
+    N3P_E_CALLBACK = -5,    /* a user callback returned non-zero */
+    N3P_E_HIP = -6,         /* a HIP runtime call failed */
+    N3P_E_TIMEOUT = -7      /* a device-side bounded wait expired (never expected) */
+} n3p_status;
+
+/* Human-readable name of a status code (static storage). */
+N3P_API const char *n3p_status_str(int status);
+/* Library version string, e.g. "n3p 0.1.0 gfx950". */
+N3P_API const char *n3p_version(void);
+
+/* ----------------------------------------------------------------- enums */
+/* Precision in which the Jacobian copy is stored and LU-factored.  FP16 and
+ * BF16 give the three-precision method of Section 2 (half precision as in
+ * Table 1; BF16 has FP32's range); FP32 and FP64 give the comparison points
+ * (Newton with a single- or double-precision factorisation, Section 1.3). */
+typedef enum n3p_prec { N3P_FP16 = 0, N3P_BF16 = 1, N3P_FP32 = 2, N3P_FP64 = 3 } n3p_prec;
+
+/* Linear solver for the step equation J s = -F.
+ *   N3P_IR        iterative refinement with the low-precision factors
+ *                 (the IR algorithm of Section 2.2; stopping rule of Section 3.1)
+ *   N3P_GMRES_IR  GMRES left-preconditioned by the low-precision factors
+ *                 computes each IR correction (end of Section 2.2)
+ *   N3P_DIRECT    one triangular solve with the factors (two-precision
+ *                 Newton of Section 1.3: the "F16"/"F32"/"F64" columns of
+ *                 Tables 2 and 3) */
+typedef enum n3p_linsolver { N3P_IR = 0, N3P_GMRES_IR = 1, N3P_DIRECT = 2 } n3p_linsolver;
+
+/* Half-precision range handling (Section 1.2 warns about the range of half
+ * precision; eqs. (2.17)-(2.18) scale the right-hand side).
+ *   N3P_SCALE_AUTO  FP16: power-of-two column scaling of the half copy,
+ *                   retried once with a smaller target on overflow; other
+ *                   precisions: no scaling
+ *   N3P_SCALE_NONE  plain rounding I_s^h(J) */
+typedef enum n3p_scale { N3P_SCALE_AUTO = 0, N3P_SCALE_NONE = 1 } n3p_scale;
+
+/* --------------------------------------------------------------- options */
+typedef struct n3p_options {
+    double tau_r;            /* relative nonlinear tolerance (default 1e-10) */
+    double tau_a;            /* absolute nonlinear tolerance (default 0) */
+    double tau_abs_override; /* if >= 0: stop at ||F|| <= this, ignoring tau_r/tau_a
+                                (resuming a solve from a saved iterate); default -1 */
+    double eta;              /* linear relative residual target eta_J, eq. (2.3)
+                                (default 1e-6, Section 3.1) */
+    int maxit;               /* maximum Newton steps (default 20) */
+    int max_ir_sweeps;       /* maximum IR sweeps / GMRES-IR outer sweeps (default 10) */
+    int gmres_restart;       /* GMRES Krylov dimension m (default 20, at most 64) */
+    double gmres_tol;        /* GMRES relative tolerance on the preconditioned
+                                residual (default 1e-4) */
+    int gmres_max_restarts;  /* restart cycles per GMRES call (default 10) */
+    int scale_mode;          /* n3p_scale (default N3P_SCALE_AUTO) */
+    int timing;              /* 1: record per-phase times in the report (adds
+                                event records; default 1) */
+} n3p_options;
+
+/* Fill *opt with the defaults listed above. */
+N3P_API void n3p_default_options(n3p_options *opt);
+
+/* ---------------------------------------------------------------- report */
+#define N3P_MAX_HIST 64
+typedef struct n3p_report {
+    int status;                      /* n3p_status of the solve */
+    int its;                         /* Newton steps taken */
+    double f0;                       /* ||F(x_0)||_2 */
+    double fnorm;                    /* ||F(x_its)||_2 */
+    double resid_rel[N3P_MAX_HIST];  /* ||F(x_n)||_2 / ||F(x_0)||_2, n = 0..its */
+    int lin_its[N3P_MAX_HIST];       /* IR sweeps (or GMRES iterations) at step n+1 */
+    int lin_outer[N3P_MAX_HIST];     /* IR / GMRES-IR outer sweeps at step n+1 */
+    uint8_t lin_fail[N3P_MAX_HIST];  /* 1 if the linear solve at step n+1 failed */
+    uint8_t pivoted[N3P_MAX_HIST];   /* 1 if the factorisation at step n+1 needed
+                                        row interchanges */
+    double lin_rel[N3P_MAX_HIST];    /* final ||b - J u|| / ||b|| at step n+1 */
+    float ms_jac;                    /* total time building J and its copy */
+    float ms_getrf;                  /* total factorisation time */
+    float ms_solve;                  /* total linear-solver time */
+    float ms_resid;                  /* total residual + update time */
+    float ms_total;                  /* wall time of the solve on the stream */
+} n3p_report;
+
+/* --------------------------------------------------------------- problems */
+/* Residual callback: F = F(x) in FP64.  x, F are device pointers of length n.
+ * Must enqueue all work on `stream` and return 0 (non-zero aborts the solve
+ * with N3P_E_CALLBACK). */
+typedef int (*n3p_residual_fn)(void *ctx, const double *x, double *F, int64_t n, void *stream);
+/* Jacobian callback: J = F'(x), column-major FP32, device pointer, leading
+ * dimension ldj (eq. (2.1): the Jacobian is stored in single precision). */
+typedef int (*n3p_jacobian_fn)(void *ctx, const double *x, float *J, int64_t ldj, int64_t n,
+                               void *stream);
+
+typedef struct n3p_problem {
+    int kind;          /* 0 = H-equation, 1 = dense tanh, 2 = callbacks */
+    int64_t n;
+    double c;          /* H-equation parameter */
+    const double *A;   /* dense tanh: device, column-major n x n, leading dim lda */
+    const double *b;   /* dense tanh: device, length n */
+    int64_t lda;
+    n3p_residual_fn residual;
+    n3p_jacobian_fn jacobian;
+    void *ctx;
+} n3p_problem;
+
+/* Chandrasekhar H-equation, midpoint rule, eq. (3.2) of Section 3:
+ *   F(x)_i = x_i - (1 - (c/(2N)) sum_j x_j mu_i/(mu_j + mu_i))^{-1},
+ *   mu_i = (i - 1/2)/N.  Requires n >= 1 and 0 <= c < 1 (c = 1 is accepted;
+ * its Jacobian is singular at the solution). */
+N3P_API int n3p_problem_heq(n3p_problem *p, int64_t n, double c);
+/* Dense system F(x) = A x + 0.1 tanh(x) - b with Jacobian
+ * A + 0.1 diag(1 - tanh(x)^2); A, b are caller-owned device FP64 arrays that
+ * must stay valid for every solve using p. */
+N3P_API int n3p_problem_dense_tanh(n3p_problem *p, int64_t n, const double *A, int64_t lda,
+                                   const double *b);
+/* User-defined problem through the two callbacks above. */
+N3P_API int n3p_problem_callbacks(n3p_problem *p, int64_t n, n3p_residual_fn F,
+                                  n3p_jacobian_fn J, void *ctx);
+
+/* ----------------------------------------------------------- solve (main) */
+/* Device bytes needed by n3p_solve for this size / precision / solver. */
+N3P_API size_t n3p_workspace_size(int64_t n, int lu_prec, int linsolver, const n3p_options *opt);
+
+/*
+ * newton3p(F, x, tau_a, tau_r, eta_J): Algorithm 2.1 of Section 2.
+ *   evaluate F(x) (FP64); tau = tau_r ||F|| + tau_a
+ *   while ||F|| > tau:
+ *     J = F'(x) stored FP32; J_h = I_s^h(J) in lu_prec (column-scaled for FP16)
+ *     factor J_h (partial pivoting); find s with ||J s + F|| <= eta ||F||
+ *     by `linsolver` on the unit right-hand side -F/||F|| (eqs. (2.17)-(2.18));
+ *     x += s (FP64); evaluate F(x)
+ * x: device FP64 array of length p->n, the initial iterate on entry and the
+ * last iterate on exit.  opt may be NULL (defaults).  ws/ws_bytes: device
+ * workspace of at least n3p_workspace_size bytes.  rep: host struct filled
+ * on return (may be NULL).  Synchronises `stream` before returning.
+ * Returns N3P_OK, N3P_NOT_CONVERGED or an error code.  A linear-solver
+ * failure is not an error: as in Section 3.1 the best iterate is used,
+ * rep->lin_fail is set and the Newton iteration continues.
+ */
+N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int linsolver,
+                      const n3p_options *opt, void *ws, size_t ws_bytes, void *stream,
+                      n3p_report *rep);
+
+/* ---------------------------------------------------- component entry points */
+/* Device bytes needed by n3p_getrf / n3p_getrs for size n in `prec`. */
+N3P_API size_t n3p_getrf_workspace_size(int64_t n, int prec);
+
+/*
+ * LU factorisation with partial pivoting, P A = L U (Gaussian elimination,
+ * Section 1.3; the half-precision factorisation of Section 2).  A: device,
+ * n x n, column-major, leading dimension lda, element type given by prec
+ * (FP16 = IEEE binary16, BF16 = bfloat16, FP32, FP64); overwritten by L
+ * (unit lower, below the diagonal) and U.  ipiv: device int32[n], 0-based.
+ * Low-precision products accumulate in FP32 (FP64 for FP64) and are rounded
+ * to prec when stored.  Pivots: the largest magnitude in the column, ties to
+ * the lowest row.  *info (host): 0, or k+1 if U(k,k) is exactly zero, or -1
+ * if the factors are not finite.  Synchronises the stream.  The input is
+ * factored as given (no scaling); n3p_solve adds the column scaling.
+ */
+N3P_API int n3p_getrf(int prec, int64_t n, void *A, int64_t lda, int32_t *ipiv, int *info,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Solve A x = b with the factors from n3p_getrf: x = U^{-1} L^{-1} P b.  The
+ * factors are read in `prec` and promoted to FP32 (FP64 for FP64 factors) on
+ * the fly (Section 2.3); b is a device FP32 vector (FP64 when prec is FP64),
+ * overwritten by x.  Asynchronous.
+ */
+N3P_API int n3p_getrs(int prec, int64_t n, const void *LU, int64_t lda, const int32_t *ipiv,
+                      void *b, void *ws, size_t ws_bytes, void *stream);
+
+/* r = b - A u for FP32 column-major A (n x n, leading dim lda) and FP32
+ * vectors (device); products accumulate in FP64, r is rounded to FP32.  The
+ * residual of the IR algorithm, Section 2.2.  Asynchronous. */
+N3P_API int n3p_gemv_resid_f32(int64_t n, const float *A, int64_t lda, const float *u,
+                               const float *b, float *r, void *ws, size_t ws_bytes, void *stream);
+
+/* H-equation residual, eq. (3.2): F (and D_i = the bracket) in FP64, device
+ * arrays of length n (D may be NULL).  Asynchronous. */
+N3P_API int n3p_heq_residual(int64_t n, double c, const double *x, double *F, double *D,
+                             void *stream);
+/* H-equation Jacobian J_ij = delta_ij - (c/(2N)) mu_i/(mu_i+mu_j) / D_i^2
+ * computed in FP64 and stored FP32 (eq. (2.1)); device, column-major, ldj.
+ * Needs D from n3p_heq_residual.  Asynchronous. */
+N3P_API int n3p_heq_jacobian(int64_t n, double c, const double *D, float *J, int64_t ldj,
+                             void *stream);
+
+/*
+ * Iterative refinement for A u = b (the IR algorithm of Section 2.2) with
+ * A FP32 (device, n x n, lda), b FP32 (device), and factors LU/ipiv of a
+ * low-precision copy of A from n3p_getrf in `prec` (column scale vector
+ * `colscale` may be NULL; if given, the factors are those of A*diag(colscale)).
+ * u (device FP32) is the initial iterate on entry and the result on exit.
+ * Stops when ||b - A u|| < tol ||b||, after max_sweeps sweeps, or when the
+ * residual norm increases (failure: the best iterate is returned), as in
+ * Section 3.1.  *sweeps, *failed, *rel_res (host) report the outcome.
+ * Synchronises the stream.
+ */
+N3P_API int n3p_ir(int prec, int64_t n, const float *A, int64_t lda, const void *LU,
+                   int64_t ldlu, const int32_t *ipiv, const float *colscale, const float *b,
+                   float *u, double tol, int max_sweeps, int *sweeps, int *failed,
+                   double *rel_res, void *ws, size_t ws_bytes, void *stream);
+
+/* GMRES-IR: as n3p_ir, but each correction solves M^{-1} A d = M^{-1} r
+ * (M = the low-precision LU) with restarted GMRES(m), modified Gram-Schmidt,
+ * relative tolerance gmres_tol (end of Section 2.2).  *gmres_its (host)
+ * returns the total Arnoldi steps.  Synchronises the stream. */
+N3P_API int n3p_gmres_ir(int prec, int64_t n, const float *A, int64_t lda, const void *LU,
+                         int64_t ldlu, const int32_t *ipiv, const float *colscale,
+                         const float *b, float *u, double tol, int max_outer, int m,
+                         double gmres_tol, int *sweeps, int *gmres_its, int *failed,
+                         double *rel_res, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for n3p_ir / n3p_gmres_ir / n3p_gemv_resid_f32 at size n
+ * with Krylov dimension m (ignored for IR). */
+N3P_API size_t n3p_linsolve_workspace_size(int64_t n, int m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* N3P_H */

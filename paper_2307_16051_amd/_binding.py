@@ -1,0 +1,315 @@
+"""ctypes binding of libn3p (argument marshalling only).
+
+Names follow the C ABI in include/n3p.h.  Tensors must be CUDA (HIP) tensors
+on the current device; the binding passes their data pointers and the
+current torch stream.  Workspaces are allocated with torch (the library never
+allocates device memory).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional
+
+import torch
+
+FP16, BF16, FP32, FP64 = 0, 1, 2, 3
+IR, GMRES_IR, DIRECT = 0, 1, 2
+SCALE_AUTO, SCALE_NONE = 0, 1
+MAX_HIST = 64
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libn3p.so")
+
+if not os.path.exists(lib_path):
+    raise ImportError(
+        "libn3p.so is not built (%s); run `python -c \"import __graft_entry__ as g; g.build()\"`"
+        % lib_path)
+
+lib = ctypes.CDLL(lib_path)
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_f64 = ctypes.c_double
+_int = ctypes.c_int
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tau_r", _f64), ("tau_a", _f64), ("tau_abs_override", _f64), ("eta", _f64),
+                ("maxit", _int), ("max_ir_sweeps", _int), ("gmres_restart", _int),
+                ("gmres_tol", _f64), ("gmres_max_restarts", _int), ("scale_mode", _int),
+                ("timing", _int)]
+
+    @classmethod
+    def default(cls, **kw) -> "Options":
+        o = cls()
+        lib.n3p_default_options(ctypes.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise AttributeError(k)
+            setattr(o, k, v)
+        return o
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("status", _int), ("its", _int), ("f0", _f64), ("fnorm", _f64),
+                ("resid_rel", _f64 * MAX_HIST), ("lin_its", _int * MAX_HIST),
+                ("lin_outer", _int * MAX_HIST), ("lin_fail", ctypes.c_uint8 * MAX_HIST),
+                ("pivoted", ctypes.c_uint8 * MAX_HIST), ("lin_rel", _f64 * MAX_HIST),
+                ("ms_jac", ctypes.c_float), ("ms_getrf", ctypes.c_float),
+                ("ms_solve", ctypes.c_float), ("ms_resid", ctypes.c_float),
+                ("ms_total", ctypes.c_float)]
+
+
+RESID_FN = ctypes.CFUNCTYPE(_int, _vp, _vp, _vp, _i64, _vp)
+JAC_FN = ctypes.CFUNCTYPE(_int, _vp, _vp, _vp, _i64, _i64, _vp)
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("kind", _int), ("n", _i64), ("c", _f64), ("A", _vp), ("b", _vp), ("lda", _i64),
+                ("residual", RESID_FN), ("jacobian", JAC_FN), ("ctx", _vp)]
+
+
+@dataclasses.dataclass
+class Report:
+    status: int
+    its: int
+    f0: float
+    fnorm: float
+    resid_rel: List[float]
+    lin_its: List[int]
+    lin_outer: List[int]
+    lin_fail: List[bool]
+    pivoted: List[bool]
+    lin_rel: List[float]
+    ms_jac: float
+    ms_getrf: float
+    ms_solve: float
+    ms_resid: float
+    ms_total: float
+
+    @classmethod
+    def from_c(cls, r: _Report) -> "Report":
+        k = r.its
+        return cls(status=r.status, its=k, f0=r.f0, fnorm=r.fnorm,
+                   resid_rel=list(r.resid_rel[: k + 1]), lin_its=list(r.lin_its[:k]),
+                   lin_outer=list(r.lin_outer[:k]), lin_fail=[bool(v) for v in r.lin_fail[:k]],
+                   pivoted=[bool(v) for v in r.pivoted[:k]], lin_rel=list(r.lin_rel[:k]),
+                   ms_jac=r.ms_jac, ms_getrf=r.ms_getrf, ms_solve=r.ms_solve,
+                   ms_resid=r.ms_resid, ms_total=r.ms_total)
+
+
+class N3PError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__("%s: %s (%d)" % (where, status_str(status), status))
+        self.status = status
+
+
+def _setup():
+    L = lib
+    L.n3p_status_str.restype = ctypes.c_char_p
+    L.n3p_status_str.argtypes = [_int]
+    L.n3p_version.restype = ctypes.c_char_p
+    L.n3p_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.n3p_default_options.restype = None
+    L.n3p_problem_heq.argtypes = [ctypes.POINTER(_Problem), _i64, _f64]
+    L.n3p_problem_dense_tanh.argtypes = [ctypes.POINTER(_Problem), _i64, _vp, _i64, _vp]
+    L.n3p_problem_callbacks.argtypes = [ctypes.POINTER(_Problem), _i64, RESID_FN, JAC_FN, _vp]
+    L.n3p_workspace_size.argtypes = [_i64, _int, _int, ctypes.POINTER(Options)]
+    L.n3p_workspace_size.restype = ctypes.c_size_t
+    L.n3p_solve.argtypes = [ctypes.POINTER(_Problem), _vp, _int, _int, ctypes.POINTER(Options),
+                            _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_Report)]
+    L.n3p_getrf_workspace_size.argtypes = [_i64, _int]
+    L.n3p_getrf_workspace_size.restype = ctypes.c_size_t
+    L.n3p_getrf.argtypes = [_int, _i64, _vp, _i64, _vp, _ip, _vp, ctypes.c_size_t, _vp]
+    L.n3p_getrs.argtypes = [_int, _i64, _vp, _i64, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.n3p_gemv_resid_f32.argtypes = [_i64, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.n3p_heq_residual.argtypes = [_i64, _f64, _vp, _vp, _vp, _vp]
+    L.n3p_heq_jacobian.argtypes = [_i64, _f64, _vp, _vp, _i64, _vp]
+    L.n3p_linsolve_workspace_size.argtypes = [_i64, _int]
+    L.n3p_linsolve_workspace_size.restype = ctypes.c_size_t
+    L.n3p_ir.argtypes = [_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _f64, _int, _ip, _ip,
+                         _dp, _vp, ctypes.c_size_t, _vp]
+    L.n3p_gmres_ir.argtypes = [_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _f64, _int,
+                               _int, _f64, _ip, _ip, _ip, _dp, _vp, ctypes.c_size_t, _vp]
+    for name in ("n3p_problem_heq", "n3p_problem_dense_tanh", "n3p_problem_callbacks",
+                 "n3p_solve", "n3p_getrf", "n3p_getrs", "n3p_gemv_resid_f32", "n3p_heq_residual",
+                 "n3p_heq_jacobian", "n3p_ir", "n3p_gmres_ir"):
+        getattr(L, name).restype = _int
+
+
+_setup()
+
+_TORCH_DT = {FP16: torch.float16, BF16: torch.bfloat16, FP32: torch.float32, FP64: torch.float64}
+
+
+def status_str(st: int) -> str:
+    return lib.n3p_status_str(st).decode()
+
+
+def version() -> str:
+    return lib.n3p_version().decode()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return t.data_ptr()
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _check(st: int, where: str, ok=(0,)):
+    if st not in ok:
+        raise N3PError(st, where)
+    return st
+
+
+def workspace_size(n: int, prec: int = FP16, solver: int = IR, opts: Optional[Options] = None) -> int:
+    return int(lib.n3p_workspace_size(n, prec, solver, ctypes.byref(opts) if opts else None))
+
+
+def solve(problem: "_Problem", x: torch.Tensor, prec: int = FP16, solver: int = IR,
+          opts: Optional[Options] = None, ws: Optional[torch.Tensor] = None,
+          raise_on_error: bool = True) -> Report:
+    """n3p_solve: x (FP64 device, length n) is the initial iterate and the result."""
+    opts = opts or Options.default()
+    n = problem.n
+    if x.dtype != torch.float64 or x.numel() != n or not x.is_contiguous():
+        raise ValueError("x must be a contiguous FP64 device tensor of length n")
+    need = workspace_size(n, prec, solver, opts)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, x.device)
+    rep = _Report()
+    st = lib.n3p_solve(ctypes.byref(problem), _ptr(x), prec, solver, ctypes.byref(opts),
+                       _ptr(ws), ws.numel(), _stream(), ctypes.byref(rep))
+    if raise_on_error:
+        _check(st, "n3p_solve", ok=(0, 1))
+    return Report.from_c(rep)
+
+
+def solve_heq(n: int, c: float, x: Optional[torch.Tensor] = None, prec: int = FP16,
+              solver: int = IR, opts: Optional[Options] = None, device="cuda",
+              ws: Optional[torch.Tensor] = None):
+    """H-equation (eq. (3.2)) from x0 = ones unless x is given; returns (x, report)."""
+    p = _Problem()
+    _check(lib.n3p_problem_heq(ctypes.byref(p), n, c), "n3p_problem_heq")
+    if x is None:
+        x = torch.ones(n, dtype=torch.float64, device=device)
+    rep = solve(p, x, prec, solver, opts, ws)
+    return x, rep
+
+
+def solve_dense_tanh(A: torch.Tensor, b: torch.Tensor, x: torch.Tensor, prec: int = FP16,
+                     solver: int = IR, opts: Optional[Options] = None,
+                     ws: Optional[torch.Tensor] = None):
+    """F(x) = A x + 0.1 tanh(x) - b; A FP64 column-major (A.T contiguous) on the device."""
+    n = x.numel()
+    if A.dtype != torch.float64 or A.shape != (n, n) or A.stride() != (1, n):
+        raise ValueError("A must be an n x n FP64 column-major device tensor")
+    p = _Problem()
+    _check(lib.n3p_problem_dense_tanh(ctypes.byref(p), n, _ptr(A), n, _ptr(b)),
+           "n3p_problem_dense_tanh")
+    rep = solve(p, x, prec, solver, opts, ws)
+    return x, rep
+
+
+def _colmajor(A: torch.Tensor):
+    n = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != n or A.stride() != (1, n):
+        raise ValueError("expected a square column-major tensor (A.T contiguous)")
+    return n
+
+
+def getrf(A: torch.Tensor, prec: Optional[int] = None):
+    """n3p_getrf in place on a column-major device matrix; returns (ipiv, info)."""
+    n = _colmajor(A)
+    if prec is None:
+        prec = {v: k for k, v in _TORCH_DT.items()}[A.dtype]
+    ipiv = torch.empty(n, dtype=torch.int32, device=A.device)
+    ws = _ws(lib.n3p_getrf_workspace_size(n, prec), A.device)
+    info = ctypes.c_int(0)
+    st = lib.n3p_getrf(prec, n, _ptr(A), n, _ptr(ipiv), ctypes.byref(info), _ptr(ws), ws.numel(),
+                       _stream())
+    _check(st, "n3p_getrf", ok=(0, -3, -4))
+    return ipiv, info.value
+
+
+def getrs(LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Tensor, prec: Optional[int] = None):
+    """n3p_getrs: b (FP32, or FP64 for FP64 factors) is overwritten by the solution."""
+    n = _colmajor(LU)
+    if prec is None:
+        prec = {v: k for k, v in _TORCH_DT.items()}[LU.dtype]
+    ws = _ws(lib.n3p_getrf_workspace_size(n, prec), LU.device)
+    _check(lib.n3p_getrs(prec, n, _ptr(LU), n, _ptr(ipiv), _ptr(b), _ptr(ws), ws.numel(),
+                         _stream()), "n3p_getrs")
+    return b
+
+
+def gemv_resid(A: torch.Tensor, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    n = _colmajor(A)
+    r = torch.empty_like(b)
+    ws = _ws(8 * max(256, n * ((n + 255) // 256)), A.device)
+    _check(lib.n3p_gemv_resid_f32(n, _ptr(A), n, _ptr(u), _ptr(b), _ptr(r), _ptr(ws), ws.numel(),
+                                  _stream()), "n3p_gemv_resid_f32")
+    return r
+
+
+def heq_residual(x: torch.Tensor, c: float):
+    n = x.numel()
+    F = torch.empty_like(x)
+    D = torch.empty_like(x)
+    _check(lib.n3p_heq_residual(n, c, _ptr(x), _ptr(F), _ptr(D), _stream()), "n3p_heq_residual")
+    return F, D
+
+
+def heq_jacobian(D: torch.Tensor, c: float) -> torch.Tensor:
+    n = D.numel()
+    J = torch.empty((n, n), dtype=torch.float32, device=D.device).t()  # column-major
+    _check(lib.n3p_heq_jacobian(n, c, _ptr(D), _ptr(J), n, _stream()), "n3p_heq_jacobian")
+    return J
+
+
+def _lin_args(A, LU, ipiv, colscale, prec):
+    n = _colmajor(A)
+    _colmajor(LU)
+    if prec is None:
+        prec = {v: k for k, v in _TORCH_DT.items()}[LU.dtype]
+    return n, prec, _ptr(ipiv) if ipiv is not None else None, _ptr(colscale) if colscale is not None else None
+
+
+def ir(A: torch.Tensor, LU: torch.Tensor, ipiv, b: torch.Tensor, u: torch.Tensor,
+       tol: float = 1e-6, max_sweeps: int = 10, colscale=None, prec: Optional[int] = None):
+    """n3p_ir; returns (sweeps, failed, rel_res); u is updated in place."""
+    n, prec, pp, cp = _lin_args(A, LU, ipiv, colscale, prec)
+    ws = _ws(lib.n3p_linsolve_workspace_size(n, 1), A.device)
+    sw, fl, rr = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib.n3p_ir(prec, n, _ptr(A), n, _ptr(LU), n, pp, cp, _ptr(b), _ptr(u), tol, max_sweeps,
+                      ctypes.byref(sw), ctypes.byref(fl), ctypes.byref(rr), _ptr(ws), ws.numel(),
+                      _stream()), "n3p_ir")
+    return sw.value, bool(fl.value), rr.value
+
+
+def gmres_ir(A: torch.Tensor, LU: torch.Tensor, ipiv, b: torch.Tensor, u: torch.Tensor,
+             tol: float = 1e-6, max_outer: int = 10, m: int = 20, gmres_tol: float = 1e-4,
+             colscale=None, prec: Optional[int] = None):
+    """n3p_gmres_ir; returns (sweeps, gmres_its, failed, rel_res)."""
+    n, prec, pp, cp = _lin_args(A, LU, ipiv, colscale, prec)
+    ws = _ws(lib.n3p_linsolve_workspace_size(n, m), A.device)
+    sw, gi, fl, rr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib.n3p_gmres_ir(prec, n, _ptr(A), n, _ptr(LU), n, pp, cp, _ptr(b), _ptr(u), tol,
+                            max_outer, m, gmres_tol, ctypes.byref(sw), ctypes.byref(gi),
+                            ctypes.byref(fl), ctypes.byref(rr), _ptr(ws), ws.numel(), _stream()),
+           "n3p_gmres_ir")
+    return sw.value, gi.value, bool(fl.value), rr.value

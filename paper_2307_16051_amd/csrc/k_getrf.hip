@@ -1,0 +1,820 @@
+// k_getrf.hip -- blocked right-looking LU with partial pivoting for gfx950.
+//
+// The factorisation (Gaussian elimination, Section 1.3; the half-precision
+// factorisation J_h = L U of Section 2) runs on the padded Np x Np copy:
+//
+//   for each outer block of NB_OUT columns:
+//     for each leaf of NB_LEAF columns inside it:
+//       leaf kernel   -- factor the leaf, form L21 and the U row block
+//       inner GEMMs   -- update the rest of the outer block (K = NB_LEAF)
+//     outer GEMM      -- Schur complement of the trailing matrix (K = NB_OUT)
+//
+// Pivoting: the leaf kernel first tries the diagonal as pivot and verifies,
+// column by column, that every candidate below it is smaller in magnitude by
+// a margin (|a_ij| <= (1 - 2^-8) |a_jj|).  When that holds for every column,
+// partial pivoting (largest magnitude, ties to the lowest row) selects the
+// diagonal at every step, so the no-interchange factorisation IS the
+// partial-pivoting one.  If any column fails the test, a flag aborts the
+// remaining kernels and the host re-runs the factorisation with explicit
+// pivot searches and row interchanges (k_pivot_panel / k_laswp).  Near-ties
+// always take the explicit path, so rounding differences cannot change a
+// pivot decision.
+//
+// The Schur-complement GEMMs use the matrix cores: FP16/BF16 inputs with FP32
+// accumulation (v_mfma_f32_32x32x16_{f16,bf16}), rounded to the storage type
+// once per GEMM; FP32 and FP64 use v_mfma_{f32,f64}_16x16x4.
+#include <algorithm>
+
+#include "n3p_internal.hpp"
+
+namespace n3p {
+
+// =========================================================== leaf (no-swap)
+// Block b < nrt: 256 rows of L21 below the leaf; b >= nrt: 256 columns of the
+// U row block to the right of the leaf.  Every block first factors the 64x64
+// diagonal block itself (identical arithmetic in every block), so no block
+// waits for another.  The factored diagonal block goes to DG (a side buffer):
+// blocks still reading the unfactored block from A must not see it change.
+// DGprev (if non-null) is the previous leaf's diagonal block, copied into A
+// by block 0 here (nothing else touches that region during this kernel).
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__restrict__ A,
+                                                   int64_t lda, T *__restrict__ LT, int64_t k0,
+                                                   int nrt, T *__restrict__ DG,
+                                                   const T *__restrict__ DGprev, int64_t cprev,
+                                                   int *__restrict__ flags)
+{
+    typedef typename compute_of<T>::type CT;
+    constexpr int L = NB_LEAF;
+    __shared__ CT Dm[L][L + 1];
+    __shared__ int sfail;
+    if (block_flag(&flags[FLAG_FAIL])) return;
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0 && DGprev) {
+        for (int e = t; e < L * L; e += 256) {
+            const int i = e % L, j = e / L;
+            A[(cprev + i) + (cprev + j) * lda] = DGprev[i + j * L];
+        }
+    }
+    if (t == 0) sfail = 0;
+    for (int e = t; e < L * L; e += 256) {
+        const int i = e % L, j = e / L;
+        Dm[i][j] = (CT)to_f32(A[(c0 + i) + (c0 + j) * lda]);
+    }
+    __syncthreads();
+    const CT margin = (CT)(1.0 - 1.0 / 256.0);
+    const int r = t % L, g = t / L;
+    bool fail = false;
+    for (int k = 0; k < L; ++k) {
+        const CT piv = Dm[k][k];
+        CT l = 0;
+        if (!(fabs(piv) > (CT)0)) fail = true;
+        if (r > k) {
+            const CT a = Dm[r][k];
+            if (!(fabs(a) <= margin * fabs(piv))) fail = true;
+            l = a / piv;
+        }
+        __syncthreads();
+        if (r > k) {
+            if (g == 0) Dm[r][k] = l;
+            for (int j = k + 1 + g; j < L; j += 4) Dm[r][j] -= l * Dm[k][j];
+        }
+        __syncthreads();
+    }
+    if (fail) sfail = 1;
+    __syncthreads();
+    if (sfail) {
+        if (t == 0) set_flag(&flags[FLAG_FAIL], 1);
+        return;
+    }
+    if (blockIdx.x == 0) {
+        for (int e = t; e < L * L; e += 256) {
+            const int i = e % L, j = e / L;
+            DG[i + j * L] = to_store<T>((float)Dm[i][j]);
+        }
+    }
+    bool bad = false;
+    if ((int)blockIdx.x < nrt) {
+        // L21 row i: solve l U11 = a (row vector), checking each candidate
+        const int64_t i = c0 + L + (int64_t)blockIdx.x * 256 + t;
+        if (i < Np) {
+            CT x[L];
+#pragma unroll
+            for (int j = 0; j < L; ++j) x[j] = (CT)to_f32(A[i + (c0 + j) * lda]);
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                CT s = x[j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) s -= x[k] * Dm[k][j];
+                if (!(fabs(s) <= margin * fabs(Dm[j][j]))) fail = true;
+                x[j] = s / Dm[j][j];
+            }
+            T *lt = LT + i * (int64_t)NB_OUT + (c0 - k0);
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                const T v = to_store<T>((float)x[j]);
+                if (!isfinite((float)x[j])) bad = true;
+                A[i + (c0 + j) * lda] = v;
+                lt[j] = v;
+            }
+        }
+        if (fail) set_flag(&flags[FLAG_FAIL], 1);
+    } else {
+        // U12 column jc: forward substitution with the unit lower L11
+        const int64_t jc = c0 + L + (int64_t)(blockIdx.x - nrt) * 256 + t;
+        if (jc < Np) {
+            T *col = A + jc * lda + c0;
+            CT y[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k) y[k] = (CT)to_f32(col[k]);
+#pragma unroll
+            for (int k = 1; k < L; ++k) {
+                CT s = y[k];
+#pragma unroll
+                for (int m = 0; m < k; ++m) s -= Dm[k][m] * y[m];
+                y[k] = s;
+            }
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                if (!isfinite((float)y[k])) bad = true;
+                col[k] = to_store<T>((float)y[k]);
+            }
+        }
+    }
+    if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
+}
+
+// copy a 64x64 diagonal block from DG into A (the last leaf's block)
+template <typename T>
+__global__ __launch_bounds__(256) void k_put_diag(int64_t c0, T *__restrict__ A, int64_t lda,
+                                                  const T *__restrict__ DG, const int *flags)
+{
+    if (ld_flag(&flags[FLAG_FAIL])) return;
+    for (int e = threadIdx.x; e < NB_LEAF * NB_LEAF; e += 256) {
+        const int i = e % NB_LEAF, j = e / NB_LEAF;
+        A[(c0 + i) + (c0 + j) * lda] = DG[i + j * NB_LEAF];
+    }
+}
+
+// ============================================= Schur GEMM, FP16/BF16 matrix cores
+// C[M x N] -= At^T B, where At holds A row-major (row i at At + i*ldat, K
+// contiguous) and B is column-major (column j at B + j*ldb, K contiguous).
+// Block tile TM x TN, WGM x WGN waves, K staged through LDS in KC chunks,
+// double-buffered.  Each wave owns (TM/WGM) x (TN/WGN) as 32x32 fragments.
+template <typename T> struct mfma32;
+template <> struct mfma32<f16> {
+    typedef h8 vec;
+    static __device__ __forceinline__ f32x16 op(vec a, vec b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct mfma32<bf16> {
+    typedef b8 vec;
+    static __device__ __forceinline__ f32x16 op(vec a, vec b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename T, int TM, int TN, int WGM, int WGN, int KC>
+__global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
+                                                          const T *__restrict__ At, int64_t ldat,
+                                                          const T *__restrict__ B, int64_t ldb,
+                                                          T *__restrict__ C, int64_t ldc,
+                                                          int *__restrict__ flags, int check_abort)
+{
+    typedef typename mfma32<T>::vec vec;
+    constexpr int NT = WGM * WGN * 64;
+    constexpr int WM = TM / WGM, WN = TN / WGN, FM = WM / 32, FN = WN / 32;
+    constexpr int KP = KC + 8;          // padded LDS row (elements): 16-byte skew
+    constexpr int CPR = KC / 8;         // 16-byte chunks per row
+    constexpr int ACH = TM * CPR / NT;  // A chunks per thread per stage
+    constexpr int BCH = TN * CPR / NT;
+    static_assert(ACH * NT == TM * CPR && BCH * NT == TN * CPR, "tile/thread mismatch");
+    __shared__ __attribute__((aligned(16))) T As[2][TM * KP];
+    __shared__ __attribute__((aligned(16))) T Bs[2][TN * KP];
+
+    if (check_abort && block_flag(&flags[FLAG_FAIL])) return;
+    const int ntm = M / TM, ntn = N / TN, nt = ntm * ntn;
+    const int bid = blockIdx.x;
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs;
+    // give each XCD a contiguous run of tiles (shared B columns stay in its L2)
+    int tile = bid;
+    if ((nt & 7) == 0) tile = (bid & 7) * (nt >> 3) + (bid >> 3);
+    const int tm = tile % ntm, tn = tile / ntm;
+    const int row0 = tm * TM, col0 = tn * TN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[a][b][q] = 0.0f;
+
+    uint4 ra[ACH], rb[BCH];
+#define N3P_GLOAD(kk_)                                                                        \
+    do {                                                                                      \
+        _Pragma("unroll") for (int c = 0; c < ACH; ++c) {                                     \
+            const int ch = tid + c * NT, r = ch / CPR, seg = ch % CPR;                        \
+            ra[c] = *(const uint4 *)(At + (int64_t)(row0 + r) * ldat + (kk_) + seg * 8);      \
+        }                                                                                     \
+        _Pragma("unroll") for (int c = 0; c < BCH; ++c) {                                     \
+            const int ch = tid + c * NT, r = ch / CPR, seg = ch % CPR;                        \
+            rb[c] = *(const uint4 *)(B + (int64_t)(col0 + r) * ldb + (kk_) + seg * 8);        \
+        }                                                                                     \
+    } while (0)
+#define N3P_SSTORE(buf_)                                                                      \
+    do {                                                                                      \
+        _Pragma("unroll") for (int c = 0; c < ACH; ++c) {                                     \
+            const int ch = tid + c * NT, r = ch / CPR, seg = ch % CPR;                        \
+            *(uint4 *)(&As[(buf_)][r * KP + seg * 8]) = ra[c];                                \
+        }                                                                                     \
+        _Pragma("unroll") for (int c = 0; c < BCH; ++c) {                                     \
+            const int ch = tid + c * NT, r = ch / CPR, seg = ch % CPR;                        \
+            *(uint4 *)(&Bs[(buf_)][r * KP + seg * 8]) = rb[c];                                \
+        }                                                                                     \
+    } while (0)
+
+    N3P_GLOAD(0);
+    N3P_SSTORE(0);
+    __syncthreads();
+    int buf = 0;
+    const int lr = lane & 31, lk = (lane >> 5) * 8;
+    for (int kk = 0; kk < K; kk += KC) {
+        const bool more = kk + KC < K;
+        if (more) N3P_GLOAD(kk + KC);
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 16) {
+            vec a[FM], b[FN];
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+                a[fm] = *(const vec *)(&As[buf][(wm * WM + fm * 32 + lr) * KP + ks + lk]);
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+                b[fn] = *(const vec *)(&Bs[buf][(wn * WN + fn * 32 + lr) * KP + ks + lk]);
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = mfma32<T>::op(a[fm], b[fn], acc[fm][fn]);
+        }
+        if (more) N3P_SSTORE(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#undef N3P_GLOAD
+#undef N3P_SSTORE
+
+    // epilogue: lane holds column (lane & 31) and rows 8g + 4(lane >> 5) + q
+    typedef T t4 __attribute__((ext_vector_type(4)));
+    bool bad = false;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            const int col = col0 + wn * WN + fn * 32 + lr;
+            const int rb0 = row0 + wm * WM + fm * 32 + (lane >> 5) * 4;
+            T *cp = C + (int64_t)col * ldc;
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) {
+                t4 *p = (t4 *)(cp + rb0 + gq * 8);
+                t4 cv = *p;
+                t4 o;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float v = (float)cv[q] - acc[fm][fn][gq * 4 + q];
+                    o[q] = (T)v;
+                    bad |= !isfinite((float)o[q]);
+                }
+                *p = o;
+            }
+        }
+    if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
+}
+
+// ========================================== Schur GEMM, FP32/FP64 matrix cores
+template <typename T> struct mfma16x4;
+template <> struct mfma16x4<float> {
+    typedef f32x4 acc_t;
+    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct mfma16x4<double> {
+    typedef f64x4 acc_t;
+    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// 64x64 block tile, 4 waves of 32x32 (2x2 fragments of 16x16), KC = 16.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_mfma4(int M, int N, int K, const T *__restrict__ At,
+                                                    int64_t ldat, const T *__restrict__ B,
+                                                    int64_t ldb, T *__restrict__ C, int64_t ldc,
+                                                    int *__restrict__ flags, int check_abort)
+{
+    typedef typename mfma16x4<T>::acc_t acc_t;
+    constexpr int TM = 64, TN = 64, KC = 16;
+    __shared__ T As[KC][TM + 4];
+    __shared__ T Bs[KC][TN + 4];
+    if (check_abort && block_flag(&flags[FLAG_FAIL])) return;
+    const int ntm = M / TM, ntn = N / TN, nt = ntm * ntn;
+    int tile = blockIdx.x;
+    if ((nt & 7) == 0) tile = (blockIdx.x & 7) * (nt >> 3) + (blockIdx.x >> 3);
+    const int row0 = (tile % ntm) * TM, col0 = (tile / ntm) * TN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][b][q] = 0;
+    // loader: thread -> (row r = tid/4, k quad kq = (tid%4)*4)
+    const int lrow = tid >> 2, lkq = (tid & 3) * 4;
+    for (int kk = 0; kk < K; kk += KC) {
+        T va[4], vb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            va[q] = At[(int64_t)(row0 + lrow) * ldat + kk + lkq + q];
+            vb[q] = B[(int64_t)(col0 + lrow) * ldb + kk + lkq + q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[lkq + q][lrow] = va[q];
+            Bs[lkq + q][lrow] = vb[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 4) {
+            const int kr = ks + (lane >> 4), ci = lane & 15;
+#pragma unroll
+            for (int fm = 0; fm < 2; ++fm) {
+                const T a = As[kr][wm * 32 + fm * 16 + ci];
+#pragma unroll
+                for (int fn = 0; fn < 2; ++fn) {
+                    const T b = Bs[kr][wn * 32 + fn * 16 + ci];
+                    acc[fm][fn] = mfma16x4<T>::op(a, b, acc[fm][fn]);
+                }
+            }
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < 2; ++fn) {
+            const int col = col0 + wn * 32 + fn * 16 + (lane & 15);
+            const int rb0 = row0 + wm * 32 + fm * 16 + (lane >> 4) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T *p = C + (int64_t)col * ldc + rb0 + q;
+                const T v = *p - acc[fm][fn][q];
+                bad |= !isfinite((double)v);
+                *p = v;
+            }
+        }
+    if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
+}
+
+// ============================================ pivoting path (explicit search)
+// One workgroup factors the 64-column panel [c0, c0+64) x rows [c0, Np) with
+// partial pivoting in FP32 (FP64 for FP64 storage) on a scratch copy, four
+// columns at a time held in registers (each thread owns rows tid + 1024 q).
+// Interchanges are applied to all 64 panel columns (ipiv is global, 0-based);
+// the rest of the matrix is swapped afterwards by k_laswp.
+constexpr int PP_THREADS = 512, PP_SUB = 4;
+
+template <typename T, int R>
+__global__ __launch_bounds__(PP_THREADS) void k_pivot_panel(int64_t Np, int64_t c0,
+                                                            T *__restrict__ A, int64_t lda,
+                                                            int32_t *__restrict__ ipiv,
+                                                            T *__restrict__ LT, int64_t k0,
+                                                            typename compute_of<T>::type *__restrict__ S,
+                                                            int *__restrict__ flags)
+{
+    typedef typename compute_of<T>::type CT;
+    constexpr int L = NB_LEAF;
+    __shared__ CT red_v[PP_THREADS / 64];
+    __shared__ int red_i[PP_THREADS / 64];
+    __shared__ CT rowk[PP_SUB], rowp[PP_SUB], piv_row[PP_SUB];
+    __shared__ CT shU[PP_SUB][L];
+    __shared__ int s_p;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t m = Np - c0;
+
+    for (int64_t e = tid; e < m * L; e += PP_THREADS) {
+        const int64_t i = e % m, j = e / m;
+        S[e] = (CT)to_f32(A[(c0 + i) + (c0 + j) * lda]);
+    }
+    __syncthreads();
+
+    for (int s0 = 0; s0 < L; s0 += PP_SUB) {
+        CT v[R][PP_SUB];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int64_t ri = tid + (int64_t)q * PP_THREADS;
+#pragma unroll
+            for (int c = 0; c < PP_SUB; ++c) v[q][c] = ri < m ? S[ri + (s0 + c) * m] : (CT)0;
+        }
+#pragma unroll
+        for (int c = 0; c < PP_SUB; ++c) {
+            const int kc = s0 + c;  // panel-local pivot row/column
+            // --- pivot search: max |v|, ties -> lowest row
+            CT best = (CT)-1;
+            int bi = 0x7fffffff;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int64_t ri = tid + (int64_t)q * PP_THREADS;
+                if (ri >= kc && ri < m) {
+                    CT a = fabs(v[q][c]);
+                    if (a != a) { set_flag(&flags[FLAG_NONFINITE], 1); a = (CT)0; }
+                    if (a > best || (a == best && (int)ri < bi)) { best = a; bi = (int)ri; }
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const CT ob = __shfl_xor(best, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (lane == 0) { red_v[wv] = best; red_i[wv] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                CT b = red_v[0];
+                int ix = red_i[0];
+                for (int w = 1; w < PP_THREADS / 64; ++w)
+                    if (red_v[w] > b || (red_v[w] == b && red_i[w] < ix)) { b = red_v[w]; ix = red_i[w]; }
+                s_p = ix;
+                ipiv[c0 + kc] = (int32_t)(c0 + ix);
+            }
+            __syncthreads();
+            const int p = s_p;
+            // --- interchange rows kc and p
+            const int ok = kc % PP_THREADS, oq = kc / PP_THREADS;
+            const int pk = p % PP_THREADS, pq = p / PP_THREADS;
+            if (p != kc) {
+                if (tid == ok) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+                        if (q == oq)
+#pragma unroll
+                            for (int cc = 0; cc < PP_SUB; ++cc) rowk[cc] = v[q][cc];
+                }
+                if (tid == pk) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+                        if (q == pq)
+#pragma unroll
+                            for (int cc = 0; cc < PP_SUB; ++cc) rowp[cc] = v[q][cc];
+                }
+                // other panel columns, held in the scratch copy
+                if (tid < L && (tid < s0 || tid >= s0 + PP_SUB)) {
+                    const CT a = S[kc + (int64_t)tid * m], b = S[p + (int64_t)tid * m];
+                    S[kc + (int64_t)tid * m] = b;
+                    S[p + (int64_t)tid * m] = a;
+                }
+                __syncthreads();
+                if (tid == ok) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+                        if (q == oq)
+#pragma unroll
+                            for (int cc = 0; cc < PP_SUB; ++cc) v[q][cc] = rowp[cc];
+                }
+                if (tid == pk) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+                        if (q == pq)
+#pragma unroll
+                            for (int cc = 0; cc < PP_SUB; ++cc) v[q][cc] = rowk[cc];
+                }
+                __syncthreads();
+            }
+            // --- broadcast the pivot row
+            if (tid == ok) {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (q == oq)
+#pragma unroll
+                        for (int cc = 0; cc < PP_SUB; ++cc) piv_row[cc] = v[q][cc];
+            }
+            __syncthreads();
+            const CT pv = piv_row[c];
+            if (pv == (CT)0) {
+                if (tid == 0) atomicCAS(&flags[FLAG_ZEROPIV], 0, (int)(c0 + kc + 1));
+            } else {
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const int64_t ri = tid + (int64_t)q * PP_THREADS;
+                    if (ri > kc && ri < m) {
+                        const CT l = v[q][c] / pv;
+                        v[q][c] = l;
+#pragma unroll
+                        for (int cc = 0; cc < PP_SUB; ++cc)
+                            if (cc > c) v[q][cc] -= l * piv_row[cc];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // write the sub-slab back
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int64_t ri = tid + (int64_t)q * PP_THREADS;
+            if (ri < m)
+#pragma unroll
+                for (int c = 0; c < PP_SUB; ++c) S[ri + (s0 + c) * m] = v[q][c];
+        }
+        __syncthreads();
+        const int rest0 = s0 + PP_SUB, nrest = L - rest0;
+        if (nrest <= 0) break;
+        // U block rows [s0, s0+SUB) of the remaining panel columns
+        if (tid < nrest) {
+            const int64_t cc = rest0 + tid;
+            CT u[PP_SUB];
+#pragma unroll
+            for (int k = 0; k < PP_SUB; ++k) {
+                CT s = S[(s0 + k) + cc * m];
+#pragma unroll
+                for (int mm = 0; mm < k; ++mm) s -= S[(s0 + k) + (int64_t)(s0 + mm) * m] * u[mm];
+                u[k] = s;
+                S[(s0 + k) + cc * m] = s;
+                shU[k][tid] = s;
+            }
+        }
+        __syncthreads();
+        // rank-SUB update of the remaining panel columns, rows below the sub-slab
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int64_t ri = tid + (int64_t)q * PP_THREADS;
+            if (ri >= rest0 && ri < m) {
+                for (int cc = 0; cc < nrest; ++cc) {
+                    CT s = S[ri + (int64_t)(rest0 + cc) * m];
+#pragma unroll
+                    for (int k = 0; k < PP_SUB; ++k) s -= v[q][k] * shU[k][cc];
+                    S[ri + (int64_t)(rest0 + cc) * m] = s;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // write the factored panel back, and the L rows below the leaf into LT
+    bool bad = false;
+    for (int64_t e = tid; e < m * L; e += PP_THREADS) {
+        const int64_t i = e % m, j = e / m;
+        const T v = to_store<T>((float)S[e]);
+        if (!isfinite((float)S[e])) bad = true;
+        A[(c0 + i) + (c0 + j) * lda] = v;
+        if (i >= L) LT[(c0 + i) * (int64_t)NB_OUT + (c0 - k0) + j] = v;
+    }
+    if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
+}
+
+// Apply interchanges ipiv[k1..k2) to columns [colA, colB): one thread per column.
+template <typename T>
+__global__ void k_laswp(T *__restrict__ A, int64_t lda, const int32_t *__restrict__ ipiv,
+                        int64_t k1, int64_t k2, int64_t colA, int64_t colB)
+{
+    const int64_t col = colA + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= colB) return;
+    T *c = A + col * lda;
+    for (int64_t k = k1; k < k2; ++k) {
+        const int64_t p = ipiv[k];
+        if (p != k) {
+            const T a = c[k];
+            c[k] = c[p];
+            c[p] = a;
+        }
+    }
+}
+
+// U row block of a factored leaf: rows [c0, c0+64) x columns [c0+64, Np),
+// forward substitution with the unit lower L11 taken from A.
+template <typename T>
+__global__ __launch_bounds__(256) void k_u12(int64_t Np, int64_t c0, T *__restrict__ A, int64_t lda,
+                                             int *__restrict__ flags)
+{
+    typedef typename compute_of<T>::type CT;
+    constexpr int L = NB_LEAF;
+    __shared__ CT Dm[L][L + 1];
+    const int t = threadIdx.x;
+    for (int e = t; e < L * L; e += 256) {
+        const int i = e % L, j = e / L;
+        Dm[i][j] = (CT)to_f32(A[(c0 + i) + (c0 + j) * lda]);
+    }
+    __syncthreads();
+    const int64_t jc = c0 + L + (int64_t)blockIdx.x * 256 + t;
+    if (jc >= Np) return;
+    T *col = A + jc * lda + c0;
+    CT y[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) y[k] = (CT)to_f32(col[k]);
+#pragma unroll
+    for (int k = 1; k < L; ++k) {
+        CT s = y[k];
+#pragma unroll
+        for (int m = 0; m < k; ++m) s -= Dm[k][m] * y[m];
+        y[k] = s;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        if (!isfinite((float)y[k])) bad = true;
+        col[k] = to_store<T>((float)y[k]);
+    }
+    if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_check_finite(int64_t Np, const T *__restrict__ A,
+                                                      int64_t lda, int *__restrict__ flags)
+{
+    const int64_t j = blockIdx.x;
+    bool bad = false;
+    for (int64_t i = threadIdx.x; i < Np; i += 256) bad |= !isfinite((float)to_f32(A[i + j * lda]));
+    if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
+}
+
+// ================================================================ launchers
+template <typename T>
+static hipError_t leaf_spec_t(int64_t Np, int64_t c0, void *A, int64_t lda, void *LT, int64_t k0,
+                              void *DG, const void *DGprev, int64_t cprev, int *flags,
+                              hipStream_t s)
+{
+    const int64_t below = Np - c0 - NB_LEAF;
+    const int nrt = (int)((below + 255) / 256);
+    const int nct = nrt;
+    const unsigned grid = (unsigned)std::max(1, nrt + nct);
+    hipLaunchKernelGGL(k_leaf_spec<T>, dim3(grid), dim3(256), 0, s, Np, c0, (T *)A, lda, (T *)LT,
+                       k0, nrt, (T *)DG, (const T *)DGprev, cprev, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_spec2(int prec, int64_t Np, int64_t c0, void *A, int64_t lda, void *LT,
+                             int64_t k0, void *DG, const void *DGprev, int64_t cprev, int *flags,
+                             hipStream_t s)
+{
+    switch (prec) {
+    case N3P_FP16: return leaf_spec_t<f16>(Np, c0, A, lda, LT, k0, DG, DGprev, cprev, flags, s);
+    case N3P_BF16: return leaf_spec_t<bf16>(Np, c0, A, lda, LT, k0, DG, DGprev, cprev, flags, s);
+    case N3P_FP32: return leaf_spec_t<float>(Np, c0, A, lda, LT, k0, DG, DGprev, cprev, flags, s);
+    case N3P_FP64: return leaf_spec_t<double>(Np, c0, A, lda, LT, k0, DG, DGprev, cprev, flags, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_put_diag(int prec, int64_t c0, void *A, int64_t lda, const void *DG,
+                           const int *flags, hipStream_t s)
+{
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_put_diag<f16>, dim3(1), dim3(256), 0, s, c0, (f16 *)A, lda, (const f16 *)DG, flags); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_put_diag<bf16>, dim3(1), dim3(256), 0, s, c0, (bf16 *)A, lda, (const bf16 *)DG, flags); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_put_diag<float>, dim3(1), dim3(256), 0, s, c0, (float *)A, lda, (const float *)DG, flags); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_put_diag<double>, dim3(1), dim3(256), 0, s, c0, (double *)A, lda, (const double *)DG, flags); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int TM, int TN, int WGM, int WGN, int KC>
+static void gemm16_go(int64_t M, int64_t N, int64_t K, const void *At, int64_t ldat, const void *B,
+                      int64_t ldb, void *C, int64_t ldc, int *flags, bool ca, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((M / TM) * (N / TN));
+    hipLaunchKernelGGL((k_gemm16<T, TM, TN, WGM, WGN, KC>), dim3(grid), dim3(WGM * WGN * 64), 0, s,
+                       (int)M, (int)N, (int)K, (const T *)At, ldat, (const T *)B, ldb, (T *)C, ldc,
+                       flags, (int)ca);
+}
+
+template <typename T>
+static hipError_t gemm16_t(int64_t M, int64_t N, int64_t K, const void *At, int64_t ldat,
+                           const void *B, int64_t ldb, void *C, int64_t ldc, int *flags, bool ca,
+                           hipStream_t s)
+{
+    if (M % 64 || N % 64 || K % 32) return hipErrorInvalidValue;
+    if (M % 256 == 0 && N % 256 == 0 && M * N >= (int64_t)256 * 256 * 128)
+        gemm16_go<T, 256, 256, 2, 4, 32>(M, N, K, At, ldat, B, ldb, C, ldc, flags, ca, s);
+    else if (M % 128 == 0 && N % 128 == 0 && M * N >= (int64_t)128 * 128 * 128)
+        gemm16_go<T, 128, 128, 2, 2, 32>(M, N, K, At, ldat, B, ldb, C, ldc, flags, ca, s);
+    else
+        gemm16_go<T, 64, 64, 2, 2, 32>(M, N, K, At, ldat, B, ldb, C, ldc, flags, ca, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t gemm4_t(int64_t M, int64_t N, int64_t K, const void *At, int64_t ldat,
+                          const void *B, int64_t ldb, void *C, int64_t ldc, int *flags, bool ca,
+                          hipStream_t s)
+{
+    if (M % 64 || N % 64 || K % 16) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)((M / 64) * (N / 64));
+    hipLaunchKernelGGL(k_gemm_mfma4<T>, dim3(grid), dim3(256), 0, s, (int)M, (int)N, (int)K,
+                       (const T *)At, ldat, (const T *)B, ldb, (T *)C, ldc, flags, (int)ca);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_sub(int prec, int64_t M, int64_t N, int64_t K, const void *At, int64_t ldat,
+                           const void *B, int64_t ldb, void *C, int64_t ldc, int *flags,
+                           bool check_abort, hipStream_t s)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    switch (prec) {
+    case N3P_FP16: return gemm16_t<f16>(M, N, K, At, ldat, B, ldb, C, ldc, flags, check_abort, s);
+    case N3P_BF16: return gemm16_t<bf16>(M, N, K, At, ldat, B, ldb, C, ldc, flags, check_abort, s);
+    case N3P_FP32: return gemm4_t<float>(M, N, K, At, ldat, B, ldb, C, ldc, flags, check_abort, s);
+    case N3P_FP64: return gemm4_t<double>(M, N, K, At, ldat, B, ldb, C, ldc, flags, check_abort, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int R>
+static void pivot_panel_go(int64_t Np, int64_t c0, void *A, int64_t lda, int32_t *ipiv, void *LT,
+                           int64_t k0, void *S, int *flags, hipStream_t s)
+{
+    typedef typename compute_of<T>::type CT;
+    hipLaunchKernelGGL((k_pivot_panel<T, R>), dim3(1), dim3(PP_THREADS), 0, s, Np, c0, (T *)A, lda,
+                       ipiv, (T *)LT, k0, (CT *)S, flags);
+}
+
+template <typename T>
+static hipError_t pivot_panel_t(int64_t Np, int64_t c0, void *A, int64_t lda, int32_t *ipiv,
+                                void *LT, int64_t k0, void *S, int *flags, hipStream_t s)
+{
+    const int64_t m = Np - c0;
+    if (m <= 2 * PP_THREADS) pivot_panel_go<T, 2>(Np, c0, A, lda, ipiv, LT, k0, S, flags, s);
+    else if (m <= 4 * PP_THREADS) pivot_panel_go<T, 4>(Np, c0, A, lda, ipiv, LT, k0, S, flags, s);
+    else if (m <= 8 * PP_THREADS) pivot_panel_go<T, 8>(Np, c0, A, lda, ipiv, LT, k0, S, flags, s);
+    else if (m <= 16 * PP_THREADS) pivot_panel_go<T, 16>(Np, c0, A, lda, ipiv, LT, k0, S, flags, s);
+    else if (m <= 32 * PP_THREADS) pivot_panel_go<T, 32>(Np, c0, A, lda, ipiv, LT, k0, S, flags, s);
+    else if (m <= 64 * PP_THREADS) pivot_panel_go<T, 64>(Np, c0, A, lda, ipiv, LT, k0, S, flags, s);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_pivot_panel(int prec, int64_t Np, int64_t c0, void *A, int64_t lda,
+                              int32_t *ipiv, void *LT, int64_t k0, float *scratch, int *flags,
+                              hipStream_t s)
+{
+    switch (prec) {
+    case N3P_FP16: return pivot_panel_t<f16>(Np, c0, A, lda, ipiv, LT, k0, scratch, flags, s);
+    case N3P_BF16: return pivot_panel_t<bf16>(Np, c0, A, lda, ipiv, LT, k0, scratch, flags, s);
+    case N3P_FP32: return pivot_panel_t<float>(Np, c0, A, lda, ipiv, LT, k0, scratch, flags, s);
+    case N3P_FP64: return pivot_panel_t<double>(Np, c0, A, lda, ipiv, LT, k0, scratch, flags, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_laswp(int prec, int64_t Np, void *A, int64_t lda, const int32_t *ipiv, int64_t k1,
+                        int64_t k2, int64_t colA, int64_t colB, hipStream_t s)
+{
+    (void)Np;
+    if (colB <= colA || k2 <= k1) return hipSuccess;
+    const unsigned grid = (unsigned)((colB - colA + 255) / 256);
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_laswp<f16>, dim3(grid), dim3(256), 0, s, (f16 *)A, lda, ipiv, k1, k2, colA, colB); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_laswp<bf16>, dim3(grid), dim3(256), 0, s, (bf16 *)A, lda, ipiv, k1, k2, colA, colB); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_laswp<float>, dim3(grid), dim3(256), 0, s, (float *)A, lda, ipiv, k1, k2, colA, colB); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_laswp<double>, dim3(grid), dim3(256), 0, s, (double *)A, lda, ipiv, k1, k2, colA, colB); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_u12(int prec, int64_t Np, int64_t c0, void *A, int64_t lda, int *flags,
+                      hipStream_t s)
+{
+    const int64_t ncol = Np - c0 - NB_LEAF;
+    if (ncol <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((ncol + 255) / 256);
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_u12<f16>, dim3(grid), dim3(256), 0, s, Np, c0, (f16 *)A, lda, flags); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_u12<bf16>, dim3(grid), dim3(256), 0, s, Np, c0, (bf16 *)A, lda, flags); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_u12<float>, dim3(grid), dim3(256), 0, s, Np, c0, (float *)A, lda, flags); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_u12<double>, dim3(grid), dim3(256), 0, s, Np, c0, (double *)A, lda, flags); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_check_factor_finite(int prec, int64_t Np, const void *A, int64_t lda, int *flags,
+                                      hipStream_t s)
+{
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_check_finite<f16>, dim3((unsigned)Np), dim3(256), 0, s, Np, (const f16 *)A, lda, flags); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_check_finite<bf16>, dim3((unsigned)Np), dim3(256), 0, s, Np, (const bf16 *)A, lda, flags); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_check_finite<float>, dim3((unsigned)Np), dim3(256), 0, s, Np, (const float *)A, lda, flags); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_check_finite<double>, dim3((unsigned)Np), dim3(256), 0, s, Np, (const double *)A, lda, flags); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace n3p

@@ -1,0 +1,573 @@
+// k_problem.hip -- residuals, Jacobians, interprecision transfers, reductions.
+//
+// H-equation (Section 3, eq. (3.2)): with mu_i = (i + 1/2)/N (0-based),
+//   mu_i / (mu_i + mu_j) = (i + 1/2) / (i + j + 1),
+// so K_ij = (c/(2N)) (i + 1/2) h_{i+j} with h_k = 1/(k+1): a diagonal times a
+// Hankel matrix.  D_i = 1 - sum_j K_ij x_j and F_i = x_i - 1/D_i are formed in
+// FP64 (the residual is evaluated in double precision, Section 2); the
+// Jacobian J_ij = delta_ij - K_ij / D_i^2 is computed in FP64 and stored in
+// FP32 (eq. (2.1)), and in the same pass rounded to the factorisation
+// precision (J_h = I_s^h(J), Section 2), optionally with a power-of-two column
+// scale against the narrow FP16 range (Section 1.2, Table 1).
+#include <algorithm>
+
+#include "n3p_internal.hpp"
+
+namespace n3p {
+
+// ----------------------------------------------------------- H-equation
+// h_k = 1/(k+1), k = 0 .. 2n-2
+__global__ void k_hinv(int64_t m, double *h)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) h[k] = 1.0 / (double)(k + 1);
+}
+
+// Each block computes HR rows of D and F.  Thread t accumulates over
+// j = t, t + 256, ... in FP64; the block reduces in a fixed order.
+constexpr int HR = 16;
+
+__global__ __launch_bounds__(256) void k_heq_residual(int64_t n, double c, const double *__restrict__ x,
+                                                      const double *__restrict__ h,
+                                                      double *__restrict__ F, double *__restrict__ D)
+{
+    __shared__ double red[HR][257];
+    const int64_t i0 = (int64_t)blockIdx.x * HR;
+    const int t = threadIdx.x;
+    double acc[HR];
+#pragma unroll
+    for (int r = 0; r < HR; ++r) acc[r] = 0.0;
+    for (int64_t j = t; j < n; j += 256) {
+        const double xj = x[j];
+#pragma unroll
+        for (int r = 0; r < HR; ++r) {
+            const int64_t i = i0 + r;
+            if (i < n) acc[r] += xj * (h ? h[i + j] : 1.0 / (double)(i + j + 1));
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < HR; ++r) red[r][t] = acc[r];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int r = 0; r < HR; ++r) red[r][t] += red[r][t + w];
+        }
+        __syncthreads();
+    }
+    if (t < HR) {
+        const int64_t i = i0 + t;
+        if (i < n) {
+            const double wgt = c / (2.0 * (double)n);
+            const double d = 1.0 - wgt * ((double)i + 0.5) * red[t][0];
+            if (D) D[i] = d;
+            F[i] = x[i] - 1.0 / d;
+        }
+    }
+}
+
+// Column-scale exponent: scale 2^e maps the column max m into
+// [2^(tl-1), 2^tl).  A zero column keeps scale 1.
+__device__ __forceinline__ float col_scale_from_max(float m, float target_log2)
+{
+    if (!(m > 0.0f) || !isfinite(m)) return 1.0f;
+    int E;
+    frexpf(m, &E);  // m = f 2^E, f in [0.5, 1)
+    int e = (int)target_log2 - E;
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    return ldexpf(1.0f, e);
+}
+
+template <typename T>
+__device__ __forceinline__ T cvt_out(float v) { return (T)v; }
+template <>
+__device__ __forceinline__ double cvt_out<double>(float v) { return (double)v; }
+
+// Block max-reduction helper (256 threads).
+__device__ __forceinline__ float block_max_256(float v, float *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] = fmaxf(sh[t], sh[t + w]);
+        __syncthreads();
+    }
+    float r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Fused H-equation Jacobian: one block per column j of the padded Np x Np
+// matrix.  Writes J (FP32, rows < n) and the factorisation copy Ah (type T,
+// Np rows, identity padding) with column scale colscale[j] (if non-null).
+template <typename T>
+__global__ __launch_bounds__(256) void k_heq_jac_round(int64_t n, int64_t Np, double c,
+                                                       const double *__restrict__ D,
+                                                       const double *__restrict__ h,
+                                                       float *__restrict__ J, int64_t ldj,
+                                                       T *__restrict__ Ah, int64_t ldh,
+                                                       float *__restrict__ colscale,
+                                                       float target_log2, int *flags)
+{
+    __shared__ float sh[256];
+    const int64_t j = blockIdx.x;
+    const int t = threadIdx.x;
+    T *col = Ah ? Ah + j * ldh : nullptr;
+    if (j >= n) {  // padding column: e_j
+        if (col)
+            for (int64_t i = t; i < Np; i += 256) col[i] = cvt_out<T>(i == j ? 1.0f : 0.0f);
+        if (colscale && t == 0) colscale[j] = 1.0f;
+        return;
+    }
+    const double wgt = c / (2.0 * (double)n);
+    float mx = 0.0f;
+    bool bad = false;
+    for (int64_t i = t; i < n; i += 256) {
+        const double di = D[i];
+        const double kij = wgt * ((double)i + 0.5) * (h ? h[i + j] : 1.0 / (double)(i + j + 1));
+        const double v = (i == j ? 1.0 : 0.0) - kij / (di * di);
+        const float vf = (float)v;
+        if (J) J[i + j * ldj] = vf;
+        if (!isfinite(vf)) bad = true;
+        mx = fmaxf(mx, fabsf(vf));
+    }
+    if (bad && flags) set_flag(&flags[FLAG_NONFINITE], 1);
+    if (!col) return;
+    float s = 1.0f;
+    if (colscale) {
+        s = col_scale_from_max(block_max_256(mx, sh), target_log2);
+        if (t == 0) colscale[j] = s;
+    }
+    for (int64_t i = t; i < n; i += 256) {
+        // recompute in the same order so the FP32 value is identical to J's
+        const double di = D[i];
+        const double kij = wgt * ((double)i + 0.5) * (h ? h[i + j] : 1.0 / (double)(i + j + 1));
+        const float vf = (float)((i == j ? 1.0 : 0.0) - kij / (di * di));
+        col[i] = cvt_out<T>(vf * s);
+    }
+    for (int64_t i = n + t; i < Np; i += 256) col[i] = cvt_out<T>(0.0f);
+}
+
+// Generic J (FP32) -> Ah rounding with optional column scaling.
+template <typename T>
+__global__ __launch_bounds__(256) void k_round_scale(int64_t n, int64_t Np, const float *__restrict__ J,
+                                                     int64_t ldj, T *__restrict__ Ah, int64_t ldh,
+                                                     float *__restrict__ colscale, float target_log2,
+                                                     int *flags)
+{
+    __shared__ float sh[256];
+    const int64_t j = blockIdx.x;
+    const int t = threadIdx.x;
+    T *col = Ah + j * ldh;
+    if (j >= n) {
+        for (int64_t i = t; i < Np; i += 256) col[i] = cvt_out<T>(i == j ? 1.0f : 0.0f);
+        if (colscale && t == 0) colscale[j] = 1.0f;
+        return;
+    }
+    const float *src = J + j * ldj;
+    float s = 1.0f;
+    float mx = 0.0f;
+    bool bad = false;
+    for (int64_t i = t; i < n; i += 256) {
+        const float v = src[i];
+        if (!isfinite(v)) bad = true;
+        mx = fmaxf(mx, fabsf(v));
+    }
+    if (bad && flags) set_flag(&flags[FLAG_NONFINITE], 1);
+    if (colscale) {
+        s = col_scale_from_max(block_max_256(mx, sh), target_log2);
+        if (t == 0) colscale[j] = s;
+    }
+    for (int64_t i = t; i < n; i += 256) col[i] = cvt_out<T>(src[i] * s);
+    for (int64_t i = n + t; i < Np; i += 256) col[i] = cvt_out<T>(0.0f);
+}
+
+// ------------------------------------------------------------ dense tanh
+// F = A x + 0.1 tanh(x) - b: partial sums over column chunks, then a fixed
+// order reduction.  Block (rb, cb): rows [rb*256, +256), columns [cb*CH, +CH).
+constexpr int GV_ROWS = 256, GV_CH = 512;
+
+__global__ __launch_bounds__(256) void k_gemv_f64_part(int64_t n, const double *__restrict__ A,
+                                                       int64_t lda, const double *__restrict__ x,
+                                                       double *__restrict__ part)
+{
+    const int64_t i = (int64_t)blockIdx.x * GV_ROWS + threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * GV_CH;
+    const int64_t j1 = min(j0 + GV_CH, n);
+    double s = 0.0;
+    if (i < n)
+        for (int64_t j = j0; j < j1; ++j) s += A[i + j * lda] * x[j];
+    if (i < n) part[(int64_t)blockIdx.y * n + i] = s;
+}
+
+__global__ void k_dense_tanh_finish(int64_t n, int nch, const double *__restrict__ part,
+                                    const double *__restrict__ x, const double *__restrict__ b,
+                                    double *__restrict__ F)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += part[(int64_t)c * n + i];
+    F[i] = s + 0.1 * tanh(x[i]) - b[i];
+}
+
+__global__ __launch_bounds__(256) void k_dense_tanh_jac(int64_t n, const double *__restrict__ A,
+                                                        int64_t lda, const double *__restrict__ x,
+                                                        float *__restrict__ J, int64_t ldj)
+{
+    const int64_t j = blockIdx.x;
+    const double tj = tanh(x[j]);
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        double v = A[i + j * lda];
+        if (i == j) v += 0.1 * (1.0 - tj * tj);
+        J[i + j * ldj] = (float)v;
+    }
+}
+
+// ----------------------------------------------------------- reductions
+// Deterministic Euclidean norm in FP64: block partial sums of squares, then a
+// single block sums the partials in index order.
+template <typename V>
+__global__ __launch_bounds__(256) void k_sumsq_part(int64_t n, const V *__restrict__ x,
+                                                    double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + t; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = (double)x[i];
+        s += v * v;
+    }
+    sh[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_sqrt(int m, const double *__restrict__ part,
+                                                  double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int i = t; i < m; i += 256) s += part[i];
+    sh[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[0] = sqrt(sh[0]);
+}
+
+constexpr int NRM_BLOCKS = 256;
+
+// ---------------------------------------------------------- vector kernels
+__global__ void k_fill_i32(int *p, int v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float *p, float v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_iota_i32(int32_t *p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+// b = I_d^s(-F/||F||), eq. (2.17); tail [n, np) zeroed
+__global__ void k_rhs_unit(int64_t n, int64_t np, const double *F, const double *fn, float *b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)(-F[i] / fn[0]);
+    else if (i < np) b[i] = 0.0f;
+}
+// FP64 right-hand side -F/||F|| (Newton with a double-precision factorisation)
+__global__ void k_rhs_unit_f64(int64_t n, int64_t np, const double *F, const double *fn, double *b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = -F[i] / fn[0];
+    else if (i < np) b[i] = 0.0;
+}
+__global__ void k_scal_copy_f32(int64_t n, float *d, const float *s, double a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (float)((double)s[i] * a);
+}
+// x += ||F|| I_s^d(u), eq. (2.18)
+__global__ void k_newton_update_f32(int64_t n, double *x, const double *fn, const float *u)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += fn[0] * (double)u[i];
+}
+__global__ void k_newton_update_f64(int64_t n, double *x, const double *fn, const double *u)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += fn[0] * u[i];
+}
+__global__ void k_axpy_f32(int64_t n, float *y, const float *x, float a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+__global__ void k_vcopy_f32(int64_t n, float *d, const float *s)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+__global__ void k_f32_to_f64(int64_t n, const float *s, double *d)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (double)s[i];
+}
+__global__ void k_f64_to_f32(int64_t n, const double *s, float *d)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (float)s[i];
+}
+__global__ void k_copy_u32(int64_t n, uint32_t *d, const uint32_t *s)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+__global__ void k_copy_u8(int64_t n, uint8_t *d, const uint8_t *s)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+// padded copies (one block per column of the Np x Np buffer)
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_in(int64_t n, int64_t Np, const T *__restrict__ A,
+                                                int64_t lda, T *__restrict__ P)
+{
+    const int64_t j = blockIdx.x;
+    T *col = P + j * Np;
+    for (int64_t i = threadIdx.x; i < Np; i += 256) {
+        T v;
+        if (j < n) v = i < n ? A[i + j * lda] : (T)0.0f;
+        else v = (T)(i == j ? 1.0f : 0.0f);
+        col[i] = v;
+    }
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_out(int64_t n, int64_t Np, const T *__restrict__ P,
+                                                 T *__restrict__ A, int64_t lda)
+{
+    const int64_t j = blockIdx.x;
+    for (int64_t i = threadIdx.x; i < n; i += 256) A[i + j * lda] = P[i + j * Np];
+}
+
+// --------------------------------------------------------------- launchers
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_hinv(int64_t n, double *h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hinv, dim3(nblk(2 * n - 1, 256)), dim3(256), 0, s, 2 * n - 1, h);
+    return hipGetLastError();
+}
+
+// h: Hankel table from launch_hinv (2n-1 entries) or null (computed inline)
+hipError_t launch_heq_residual(int64_t n, double c, const double *x, const double *h, double *F,
+                               double *D, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_heq_residual, dim3(nblk(n, HR)), dim3(256), 0, s, n, c, x, h, F, D);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t heq_jac_round_t(int64_t n, int64_t Np, double c, const double *D,
+                                  const double *h, float *J, int64_t ldj, void *Ah, int64_t ldh,
+                                  float *colscale, float tl, int *flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_heq_jac_round<T>, dim3((unsigned)(Ah ? Np : n)), dim3(256), 0, s, n, Np,
+                       c, D, h, J, ldj, (T *)Ah, ldh, colscale, tl, flags);
+    return hipGetLastError();
+}
+
+// Fused H-equation Jacobian + rounding (declared in the host driver).
+hipError_t launch_heq_jac_round(int prec, int64_t n, int64_t Np, double c, const double *D,
+                                const double *h, float *J, int64_t ldj, void *Ah, int64_t ldh,
+                                float *colscale, float tl, int *flags, hipStream_t s)
+{
+    switch (prec) {
+    case N3P_FP16: return heq_jac_round_t<f16>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, s);
+    case N3P_BF16: return heq_jac_round_t<bf16>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, s);
+    case N3P_FP32: return heq_jac_round_t<float>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, s);
+    case N3P_FP64: return heq_jac_round_t<double>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_heq_jacobian(int64_t n, double c, const double *D, const double *h, float *J,
+                               int64_t ldj, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_heq_jac_round<float>, dim3((unsigned)n), dim3(256), 0, s, n, n, c, D, h, J,
+                       ldj, (float *)nullptr, (int64_t)0, (float *)nullptr, 0.0f, (int *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_tanh_residual(int64_t n, const double *A, int64_t lda, const double *b,
+                                      const double *x, double *F, double *part, hipStream_t s)
+{
+    const int nch = (int)((n + GV_CH - 1) / GV_CH);
+    hipLaunchKernelGGL(k_gemv_f64_part, dim3(nblk(n, GV_ROWS), nch), dim3(256), 0, s, n, A, lda,
+                       x, part);
+    hipLaunchKernelGGL(k_dense_tanh_finish, dim3(nblk(n, 256)), dim3(256), 0, s, n, nch,
+                       (const double *)part, x, b, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_tanh_jacobian(int64_t n, const double *A, int64_t lda, const double *x,
+                                      float *J, int64_t ldj, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dense_tanh_jac, dim3((unsigned)n), dim3(256), 0, s, n, A, lda, x, J, ldj);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_scale(int prec, int64_t n, int64_t Np, const float *J, int64_t ldj,
+                              void *Ah, int64_t ldh, float *colscale, float tl, int *flags,
+                              hipStream_t s)
+{
+    dim3 g((unsigned)Np), b(256);
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_round_scale<f16>, g, b, 0, s, n, Np, J, ldj, (f16 *)Ah, ldh, colscale, tl, flags); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_round_scale<bf16>, g, b, 0, s, n, Np, J, ldj, (bf16 *)Ah, ldh, colscale, tl, flags); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_round_scale<float>, g, b, 0, s, n, Np, J, ldj, (float *)Ah, ldh, colscale, tl, flags); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_round_scale<double>, g, b, 0, s, n, Np, J, ldj, (double *)Ah, ldh, colscale, tl, flags); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_copy_in(int prec, int64_t n, int64_t Np, const void *A, int64_t lda,
+                              void *Ap, hipStream_t s)
+{
+    dim3 g((unsigned)Np), b(256);
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_pad_in<f16>, g, b, 0, s, n, Np, (const f16 *)A, lda, (f16 *)Ap); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_pad_in<bf16>, g, b, 0, s, n, Np, (const bf16 *)A, lda, (bf16 *)Ap); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_pad_in<float>, g, b, 0, s, n, Np, (const float *)A, lda, (float *)Ap); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_pad_in<double>, g, b, 0, s, n, Np, (const double *)A, lda, (double *)Ap); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_copy_out(int prec, int64_t n, int64_t Np, const void *Ap, void *A,
+                               int64_t lda, hipStream_t s)
+{
+    dim3 g((unsigned)n), b(256);
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_pad_out<f16>, g, b, 0, s, n, Np, (const f16 *)Ap, (f16 *)A, lda); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_pad_out<bf16>, g, b, 0, s, n, Np, (const bf16 *)Ap, (bf16 *)A, lda); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_pad_out<float>, g, b, 0, s, n, Np, (const float *)Ap, (float *)A, lda); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_pad_out<double>, g, b, 0, s, n, Np, (const double *)Ap, (double *)A, lda); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes % 4 == 0) {
+        int64_t m = (int64_t)(bytes / 4);
+        hipLaunchKernelGGL(k_copy_u32, dim3(nblk(m, 256)), dim3(256), 0, s, m, (uint32_t *)dst,
+                           (const uint32_t *)src);
+    } else {
+        int64_t m = (int64_t)bytes;
+        hipLaunchKernelGGL(k_copy_u8, dim3(nblk(m, 256)), dim3(256), 0, s, m, (uint8_t *)dst,
+                           (const uint8_t *)src);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_nrm2_f64(int64_t n, const double *x, double *part, double *out, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>(NRM_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_sumsq_part<double>, dim3(nb), dim3(256), 0, s, n, x, part);
+    hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_nrm2_f32(int64_t n, const float *x, double *part, double *out, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>(NRM_BLOCKS, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_sumsq_part<float>, dim3(nb), dim3(256), 0, s, n, x, part);
+    hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *p, int v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iota_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+hipError_t launch_rhs_unit(int64_t n, int64_t np, const double *F, const double *fnorm, float *b,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rhs_unit, dim3(nblk(np, 256)), dim3(256), 0, s, n, np, F, fnorm, b);
+    return hipGetLastError();
+}
+hipError_t launch_rhs_unit_f64(int64_t n, int64_t np, const double *F, const double *fnorm,
+                               double *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rhs_unit_f64, dim3(nblk(np, 256)), dim3(256), 0, s, n, np, F, fnorm, b);
+    return hipGetLastError();
+}
+hipError_t launch_scal_copy_f32(int64_t n, float *dst, const float *src, double a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scal_copy_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, dst, src, a);
+    return hipGetLastError();
+}
+hipError_t launch_newton_update_f32(int64_t n, double *x, const double *fnorm, const float *u,
+                                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_newton_update_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, fnorm, u);
+    return hipGetLastError();
+}
+hipError_t launch_newton_update_f64(int64_t n, double *x, const double *fnorm, const double *u,
+                                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_newton_update_f64, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, fnorm, u);
+    return hipGetLastError();
+}
+hipError_t launch_axpy_f32(int64_t n, float *y, const float *x, float a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, y, x, a);
+    return hipGetLastError();
+}
+hipError_t launch_vcopy_f32(int64_t n, float *dst, const float *src, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vcopy_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, dst, src);
+    return hipGetLastError();
+}
+hipError_t launch_f32_to_f64(int64_t n, const float *src, double *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+hipError_t launch_f64_to_f32(int64_t n, const double *src, float *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace n3p

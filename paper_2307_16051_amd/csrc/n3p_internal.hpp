@@ -1,0 +1,180 @@
+// n3p_internal.hpp -- shared declarations of the gfx950 HIP implementation.
+//
+// Storage conventions (all kernels):
+//   * matrices are column-major; the factorisation works on an Np x Np copy
+//     with Np = n rounded up to a multiple of NB_OUT, padded with the
+//     identity (the padded LU is the LU of J plus an identity block);
+//   * "LT" is the L panel of the current outer block stored row-major
+//     (K-contiguous) so that both operands of the Schur-complement GEMM feed
+//     the matrix cores with contiguous K;
+//   * "flags" is a small int array in the workspace:
+//       [0] speculation failed (a pivot would have been interchanged)
+//       [1] non-finite value produced
+//       [2] first exactly-zero pivot (k+1), 0 if none
+//       [3] device wait expired (bounded spins)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "n3p.h"
+
+namespace n3p {
+
+constexpr int NB_OUT = 512;   // outer block: K of the big Schur-complement GEMM
+constexpr int NB_LEAF = 64;   // leaf panel width
+constexpr int TRSV_BS = 64;   // row block of the triangular solves
+constexpr int FLAG_FAIL = 0, FLAG_NONFINITE = 1, FLAG_ZEROPIV = 2, FLAG_TIMEOUT = 3;
+constexpr int NFLAGS = 16;
+
+typedef _Float16 f16;
+typedef __bf16 bf16;
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// compute type of the factorisation arithmetic for a storage type
+template <typename T> struct compute_of { typedef float type; };
+template <> struct compute_of<double> { typedef double type; };
+
+template <typename T> __device__ __forceinline__ T to_store(float v) { return (T)v; }
+template <> __device__ __forceinline__ double to_store<double>(float v) { return (double)v; }
+template <typename T> __device__ __forceinline__ T to_store_d(double v) { return (T)(float)v; }
+template <> __device__ __forceinline__ double to_store_d<double>(double v) { return v; }
+
+__device__ __forceinline__ float to_f32(f16 v) { return (float)v; }
+__device__ __forceinline__ float to_f32(bf16 v) { return (float)v; }
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ double to_f32(double v) { return v; }
+
+__device__ __forceinline__ int ld_flag(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void set_flag(int *p, int v)
+{
+    __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-uniform read of a device flag: thread 0 reads, the value is broadcast
+// through LDS, so every thread of the block takes the same early-exit branch
+// (a per-thread read could split a block around a barrier).
+__device__ __forceinline__ int block_flag(const int *p)
+{
+    __shared__ int s_flag;
+    if (threadIdx.x == 0) s_flag = ld_flag(p);
+    __syncthreads();
+    const int v = s_flag;
+    __syncthreads();
+    return v;
+}
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+inline size_t elem_size(int prec)
+{
+    switch (prec) {
+    case N3P_FP16: case N3P_BF16: return 2;
+    case N3P_FP32: return 4;
+    case N3P_FP64: return 8;
+    default: return 0;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+// (defined in the .hip files; all enqueue on `s` and return hipError_t)
+
+// problem kernels
+hipError_t launch_hinv(int64_t n, double *h, hipStream_t s);  // h[k] = 1/(k+1), k < 2n-1
+hipError_t launch_heq_residual(int64_t n, double c, const double *x, const double *h, double *F,
+                               double *D, hipStream_t s);
+hipError_t launch_heq_jacobian(int64_t n, double c, const double *D, const double *h, float *J,
+                               int64_t ldj, hipStream_t s);
+hipError_t launch_heq_jac_round(int prec, int64_t n, int64_t Np, double c, const double *D,
+                                const double *h, float *J, int64_t ldj, void *Ah, int64_t ldh,
+                                float *colscale, float tl, int *flags, hipStream_t s);
+hipError_t launch_dense_tanh_residual(int64_t n, const double *A, int64_t lda, const double *b,
+                                      const double *x, double *F, double *part, hipStream_t s);
+hipError_t launch_dense_tanh_jacobian(int64_t n, const double *A, int64_t lda, const double *x,
+                                      float *J, int64_t ldj, hipStream_t s);
+// J (FP32, n x n) -> padded Np x Np copy in prec, column scales (may be null)
+hipError_t launch_round_scale(int prec, int64_t n, int64_t Np, const float *J, int64_t ldj,
+                              void *Ah, int64_t ldh, float *colscale, float target_log2,
+                              int *flags, hipStream_t s);
+// copy a caller matrix (n x n, lda) in prec into the padded Np x Np buffer and back
+hipError_t launch_pad_copy_in(int prec, int64_t n, int64_t Np, const void *A, int64_t lda,
+                              void *Ap, hipStream_t s);
+hipError_t launch_pad_copy_out(int prec, int64_t n, int64_t Np, const void *Ap, void *A,
+                               int64_t lda, hipStream_t s);
+hipError_t launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// reductions and vector kernels
+hipError_t launch_nrm2_f64(int64_t n, const double *x, double *part, double *out, hipStream_t s);
+hipError_t launch_nrm2_f32(int64_t n, const float *x, double *part, double *out, hipStream_t s);
+hipError_t launch_fill_i32(int *p, int v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
+// b = -F / ||F|| (FP64 in, FP32 out, padded tail zeroed up to np)
+hipError_t launch_rhs_unit(int64_t n, int64_t np, const double *F, const double *fnorm, float *b,
+                           hipStream_t s);
+hipError_t launch_rhs_unit_f64(int64_t n, int64_t np, const double *F, const double *fnorm,
+                               double *b, hipStream_t s);
+// dst = a * src
+hipError_t launch_scal_copy_f32(int64_t n, float *dst, const float *src, double a, hipStream_t s);
+// x += ||F|| * u  (u FP32 or FP64)
+hipError_t launch_newton_update_f32(int64_t n, double *x, const double *fnorm, const float *u,
+                                    hipStream_t s);
+hipError_t launch_newton_update_f64(int64_t n, double *x, const double *fnorm, const double *u,
+                                    hipStream_t s);
+hipError_t launch_axpy_f32(int64_t n, float *y, const float *x, float a, hipStream_t s);
+hipError_t launch_vcopy_f32(int64_t n, float *dst, const float *src, hipStream_t s);
+hipError_t launch_f32_to_f64(int64_t n, const float *src, double *dst, hipStream_t s);
+hipError_t launch_f64_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);
+
+// factorisation kernels
+hipError_t launch_leaf_spec(int prec, int64_t Np, int64_t c0, void *A, int64_t lda, void *LT,
+                            int64_t k0, int *flags, hipStream_t s);
+hipError_t launch_gemm_sub(int prec, int64_t M, int64_t N, int64_t K, const void *At,
+                           int64_t ldat, const void *B, int64_t ldb, void *C, int64_t ldc,
+                           int *flags, bool check_abort, hipStream_t s);
+hipError_t launch_pivot_panel(int prec, int64_t Np, int64_t c0, void *A, int64_t lda,
+                              int32_t *ipiv, void *LT, int64_t k0, float *scratch, int *flags,
+                              hipStream_t s);
+hipError_t launch_laswp(int prec, int64_t Np, void *A, int64_t lda, const int32_t *ipiv,
+                        int64_t k1, int64_t k2, int64_t colA, int64_t colB, hipStream_t s);
+hipError_t launch_u12(int prec, int64_t Np, int64_t c0, void *A, int64_t lda, int *flags,
+                      hipStream_t s);
+hipError_t launch_check_factor_finite(int prec, int64_t Np, const void *A, int64_t lda,
+                                      int *flags, hipStream_t s);
+
+// triangular solves and matvec
+hipError_t launch_trsv_lower(int prec, int64_t n, const void *LU, int64_t lda, const int32_t *perm,
+                             const float *b, float *y, int *sync, uint32_t epoch, int *flags,
+                             hipStream_t s);
+hipError_t launch_trsv_upper(int prec, int64_t n, const void *LU, int64_t lda, const float *y,
+                             const float *colscale, float *x, float *yscratch, int *sync,
+                             uint32_t epoch, int *flags, hipStream_t s);
+hipError_t launch_trsv_lower_f64(int64_t n, const double *LU, int64_t lda, const int32_t *perm,
+                                 const double *b, double *y, int *sync, uint32_t epoch,
+                                 int *flags, hipStream_t s);
+hipError_t launch_trsv_upper_f64(int64_t n, const double *LU, int64_t lda, const double *y,
+                                 double *x, double *yscratch, int *sync, uint32_t epoch,
+                                 int *flags, hipStream_t s);
+hipError_t launch_gemv_resid(int64_t n, const float *A, int64_t lda, const float *u,
+                             const float *b, float *r, double *part, hipStream_t s);
+// y = A v (FP32 out) for GMRES
+hipError_t launch_gemv_f32(int64_t n, const float *A, int64_t lda, const float *v, float *y,
+                           double *part, hipStream_t s);
+// modified Gram-Schmidt step: w against V[0..j], H column out, V[j+1] = w/h
+hipError_t launch_mgs(int64_t n, float *V, int64_t ldv, int j, float *w, double *Hcol,
+                      hipStream_t s);
+// d += V[0..k) y
+hipError_t launch_krylov_update(int64_t n, const float *V, int64_t ldv, int k, const double *y,
+                                float *d, hipStream_t s);
+
+size_t trsv_sync_ints(int64_t n);
+
+}  // namespace n3p

@@ -1,0 +1,76 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load and export every entry point include/n3p.h declares;
+the pure-host entry points (status strings, options, problem set-up,
+workspace sizing) are exercised directly.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "n3p.h")
+LIB = os.path.join(ROOT, "paper_2307_16051_amd", "libn3p.so")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"N3P_API\s+[^;(]*?\b(n3p_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libn3p.so not built; run __graft_entry__.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for must in ("n3p_solve", "n3p_workspace_size", "n3p_getrf", "n3p_getrs", "n3p_ir",
+                 "n3p_gmres_ir", "n3p_problem_heq", "n3p_problem_dense_tanh"):
+        assert must in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version(lib):
+    lib.n3p_status_str.restype = ctypes.c_char_p
+    lib.n3p_version.restype = ctypes.c_char_p
+    assert lib.n3p_status_str(0) == b"N3P_OK"
+    assert lib.n3p_status_str(-3) == b"N3P_E_SINGULAR"
+    assert lib.n3p_status_str(1) == b"N3P_NOT_CONVERGED"
+    assert b"gfx950" in lib.n3p_version()
+
+
+def test_binding_defaults_and_workspace():
+    import paper_2307_16051_amd as n3p
+    o = n3p.Options.default()
+    assert o.tau_r == 1e-10 and o.tau_a == 0.0 and o.eta == 1e-6
+    assert o.maxit == 20 and o.max_ir_sweeps == 10 and o.gmres_restart == 20
+    assert o.gmres_tol == 1e-4
+    # workspace: FP16 copy (2 N^2 padded) + FP32 J (4 N^2) dominate
+    n = 16384
+    ws = n3p.workspace_size(n, n3p.FP16, n3p.IR)
+    assert 6 * n * n <= ws <= 6 * n * n + 64 * 1024 * 1024
+    ws64 = n3p.workspace_size(n, n3p.FP64, n3p.DIRECT)
+    assert ws64 > 12 * n * n
+    assert n3p.workspace_size(0, n3p.FP16, n3p.IR) == 0
+    assert n3p.workspace_size(100, 7, n3p.IR) == 0
+
+
+def test_problem_setup_validates_arguments():
+    import paper_2307_16051_amd as n3p
+    from paper_2307_16051_amd import _binding as B
+    p = B._Problem()
+    assert B.lib.n3p_problem_heq(ctypes.byref(p), 256, 0.9) == 0
+    assert p.kind == 0 and p.n == 256 and p.c == 0.9
+    assert B.lib.n3p_problem_heq(ctypes.byref(p), 0, 0.9) == -1
+    assert B.lib.n3p_problem_heq(ctypes.byref(p), 10, 1.5) == -1
+    assert B.lib.n3p_problem_dense_tanh(ctypes.byref(p), 10, None, 10, None) == -1
+    assert n3p.status_str(-1) == "N3P_E_INVALID"

@@ -1,0 +1,236 @@
+"""GPU parity of the library's components against the CPU oracle.
+
+Inputs are seeded and synthetic; every expected value comes from the oracle
+or from the definition evaluated in FP64 on the CPU.  Nothing produced by the
+GPU is fed to the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import random_matrix
+
+pytestmark = pytest.mark.gpu
+
+U16 = 2.0 ** -11   # FP16 unit roundoff (IEEE binary16)
+UBF = 2.0 ** -8    # BF16 unit roundoff
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2307_16051_amd as n3p
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return n3p, torch
+
+
+def to_cm(torch, A, dtype):
+    """numpy (n x n) -> column-major device tensor (stride (1, n))."""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(A, dtype=np.float64).T)).to(
+        "cuda", dtype).t()
+
+
+def from_cm(T):
+    return T.double().cpu().numpy()
+
+
+# ------------------------------------------------------------ H-equation
+@pytest.mark.parametrize("n", [1, 7, 300, 1000])
+@pytest.mark.parametrize("c", [0.5, 0.99])
+def test_heq_residual_matches_oracle(env, n, c):
+    n3p, torch = env
+    print("case heq_residual n=%d c=%g" % (n, c), flush=True)
+    x = np.random.default_rng(n).uniform(0.8, 2.5, n)
+    F_ref, D_ref = O.heq_residual(x, c, want_d=True)
+    F, D = n3p.heq_residual(torch.from_numpy(x).cuda(), c)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(F.cpu().numpy(), F_ref, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(D.cpu().numpy(), D_ref, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [5, 257, 640])
+def test_heq_jacobian_is_fp32_rounding_of_oracle(env, n):
+    n3p, torch = env
+    c = 0.9
+    x = np.random.default_rng(n + 1).uniform(0.8, 2.5, n)
+    J_ref = O.heq_jacobian(x, c)
+    _, D = n3p.heq_residual(torch.from_numpy(x).cuda(), c)
+    J = from_cm(n3p.heq_jacobian(D, c))
+    # FP64 evaluation order differs from the oracle's by a few ulp of FP64;
+    # after rounding to FP32 the results agree to one FP32 ulp
+    assert np.all(np.abs(J - J_ref) <= 1.0 * U32 * 2 * np.abs(J_ref) + 1e-300)
+
+
+# ---------------------------------------------------------------- getrf
+def diag_dominant(n, seed):
+    A = random_matrix(n, seed)
+    return A + 2.0 * n * np.eye(n)
+
+
+@pytest.mark.parametrize("n", [64, 100, 512, 777, 1024, 1536])
+def test_getrf_fp64_no_interchange_path(env, n):
+    """Diagonally dominant: the verified no-interchange path; pivots are the identity."""
+    n3p, torch = env
+    print("case getrf_fp64_spec n=%d" % n, flush=True)
+    A = diag_dominant(n, n)
+    LU_ref, piv_ref, info_ref = O.getrf(A)
+    T = to_cm(torch, A, torch.float64)
+    ipiv, info = n3p.getrf(T)
+    assert info == info_ref == 0
+    assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
+    np.testing.assert_allclose(from_cm(T), LU_ref, rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [64, 100, 513, 1024])
+def test_getrf_fp64_pivoting_path(env, n):
+    """Gaussian matrix: explicit partial pivoting; pivots equal the oracle's."""
+    n3p, torch = env
+    print("case getrf_fp64_pivot n=%d" % n, flush=True)
+    A = random_matrix(n, 100 + n)
+    LU_ref, piv_ref, info_ref = O.getrf(A)
+    T = to_cm(torch, A, torch.float64)
+    ipiv, info = n3p.getrf(T)
+    assert info == 0
+    assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
+    np.testing.assert_allclose(from_cm(T), LU_ref, rtol=1e-9, atol=1e-9 * np.abs(LU_ref).max())
+
+
+def check_backward_error(A_in, LU, ipiv, u, nstages):
+    """|P A - L U| <= k u (|P A| + |L| |U|) elementwise, with |L| <= 1."""
+    n = A_in.shape[0]
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    p = O.perm_from_ipiv(ipiv)
+    PA = A_in[p]
+    assert np.abs(np.tril(LU, -1)).max() <= 1.0 + 4 * u
+    err = np.abs(PA - L @ U)
+    bound = (nstages + 2) * u * (np.abs(PA) + np.abs(L) @ np.abs(U))
+    ratio = (err / np.maximum(bound, 1e-300)).max()
+    assert ratio <= 1.0, ratio
+
+
+@pytest.mark.parametrize("prec,u", [("fp16", U16), ("bf16", UBF), ("fp32", U32)])
+@pytest.mark.parametrize("kind", ["dominant", "gaussian", "heq"])
+@pytest.mark.parametrize("n", [200, 1024])
+def test_getrf_low_precision_backward_error(env, prec, u, kind, n):
+    n3p, torch = env
+    print("case getrf_%s_%s n=%d" % (prec, kind, n), flush=True)
+    dt = {"fp16": torch.float16, "bf16": torch.bfloat16, "fp32": torch.float32}[prec]
+    if kind == "dominant":
+        A = diag_dominant(n, 7 + n) / (2.0 * n)
+    elif kind == "gaussian":
+        A = random_matrix(n, 9 + n)
+    else:
+        A = O.heq_jacobian(np.ones(n), 0.99)
+    T = to_cm(torch, A, dt)
+    A_in = from_cm(T)  # the rounded input actually factored
+    ipiv, info = n3p.getrf(T)
+    assert info == 0
+    piv = ipiv.cpu().numpy()
+    if kind != "gaussian":
+        assert np.array_equal(piv, np.arange(n))  # no interchange is ever the max
+    stages = (n + 511) // 512 + 8
+    check_backward_error(A_in, from_cm(T), piv, u, stages)
+
+
+def test_getrf_singular_reports_info(env):
+    n3p, torch = env
+    n = 130
+    A = random_matrix(n, 3)
+    A[:, 5] = 0.0
+    T = to_cm(torch, A, torch.float64)
+    ipiv, info = n3p.getrf(T)
+    _, _, info_ref = O.getrf(A)
+    assert info == info_ref == 6
+
+
+def test_getrf_tie_break_lowest_row(env):
+    n3p, torch = env
+    n = 96
+    A = random_matrix(n, 4) * 0.1
+    A[:, 0] = 0.0
+    A[[10, 20, 30], 0] = [-3.0, 3.0, -3.0]
+    T = to_cm(torch, A, torch.float64)
+    ipiv, info = n3p.getrf(T)
+    _, piv_ref, _ = O.getrf(A)
+    assert ipiv.cpu().numpy()[0] == piv_ref[0] == 10
+
+
+# ------------------------------------------------------------- solves
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("n", [100, 700])
+def test_getrs_with_oracle_factors(env, prec, n):
+    n3p, torch = env
+    A = random_matrix(n, 50 + n)
+    b = np.random.default_rng(n).standard_normal(n)
+    LU, piv, _ = O.getrf(A)
+    dt = {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16}[prec]
+    LUt = to_cm(torch, LU, dt)
+    LU_r = from_cm(LUt)  # factors as the GPU stores them
+    x_ref = O.getrs(LU_r, piv, b if prec == "fp64" else b.astype(np.float32).astype(np.float64))
+    vdt = torch.float64 if prec == "fp64" else torch.float32
+    bt = torch.from_numpy(b).to("cuda", vdt)
+    n3p.getrs(LUt, torch.from_numpy(piv).cuda(), bt)
+    x = bt.double().cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 2e-4
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < tol
+
+
+@pytest.mark.parametrize("n", [1, 255, 1000, 2049])
+def test_gemv_resid_matches_fp64_definition(env, n):
+    n3p, torch = env
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)).astype(np.float32)
+    u = rng.standard_normal(n).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    r_ref = b.astype(np.float64) - A.astype(np.float64) @ u.astype(np.float64)
+    r = n3p.gemv_resid(to_cm(torch, A, torch.float32), torch.from_numpy(u).cuda(),
+                       torch.from_numpy(b).cuda()).cpu().numpy().astype(np.float64)
+    scale = np.abs(b) + np.abs(A.astype(np.float64)) @ np.abs(u.astype(np.float64))
+    assert np.all(np.abs(r - r_ref) <= U32 * np.abs(r_ref) + 1e-14 * scale)
+
+
+def half_factors(J32):
+    """Oracle factorisation of the FP16-rounded matrix, factors rounded to FP16."""
+    Jh = J32.astype(np.float16).astype(np.float64)
+    LU, piv, info = O.getrf(Jh)
+    assert info == 0
+    return LU, piv
+
+
+@pytest.mark.parametrize("n,c", [(1000, 0.99), (513, 0.9)])
+def test_ir_converges_to_oracle_solution(env, n, c):
+    n3p, torch = env
+    x = O.newton_heq(n, c, floor=False).x * 0.999  # a point near the solution
+    J32 = O.heq_jacobian(x, c).astype(np.float32)
+    LU, piv = half_factors(J32)
+    b = np.random.default_rng(n).standard_normal(n).astype(np.float32)
+    b /= np.linalg.norm(b)
+    u_ref = np.linalg.solve(J32.astype(np.float64), b.astype(np.float64))
+    At = to_cm(torch, J32, torch.float32)
+    LUt = to_cm(torch, LU, torch.float16)
+    u = torch.zeros(n, dtype=torch.float32, device="cuda")
+    sw, failed, rel = n3p.ir(At, LUt, torch.from_numpy(piv).cuda(), torch.from_numpy(b).cuda(), u)
+    assert not failed and rel < 1e-6 and 1 <= sw <= 4
+    ug = u.double().cpu().numpy()
+    assert np.linalg.norm(ug - u_ref) / np.linalg.norm(u_ref) < 1e-5
+
+
+def test_gmres_ir_converges_on_ill_conditioned_heq(env):
+    n3p, torch = env
+    n, c = 1024, 0.9999
+    x = O.newton_heq(n, c, floor=False).x
+    J32 = O.heq_jacobian(x, c).astype(np.float32)
+    LU, piv = half_factors(J32)
+    b = np.random.default_rng(1).standard_normal(n).astype(np.float32)
+    b /= np.linalg.norm(b)
+    u_ref = np.linalg.solve(J32.astype(np.float64), b.astype(np.float64))
+    At = to_cm(torch, J32, torch.float32)
+    LUt = to_cm(torch, LU, torch.float16)
+    u = torch.zeros(n, dtype=torch.float32, device="cuda")
+    sw, gi, failed, rel = n3p.gmres_ir(At, LUt, torch.from_numpy(piv).cuda(),
+                                       torch.from_numpy(b).cuda(), u)
+    ug = u.double().cpu().numpy()
+    assert rel < 1e-5
+    assert np.linalg.norm(ug - u_ref) / np.linalg.norm(u_ref) < 1e-3
