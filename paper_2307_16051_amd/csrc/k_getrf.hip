@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
     if (blockIdx.x == 0) {
         for (int e = t; e < L * L; e += 256) {
             const int i = e % L, j = e / L;
-            DG[i + j * L] = to_store<T>((float)Dm[i][j]);
+            DG[i + j * L] = to_store_d<T>((double)Dm[i][j]);
         }
     }
     bool bad = false;
@@ -112,8 +112,8 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
             T *lt = LT + i * (int64_t)NB_OUT + (c0 - k0);
 #pragma unroll
             for (int j = 0; j < L; ++j) {
-                const T v = to_store<T>((float)x[j]);
-                if (!isfinite((float)x[j])) bad = true;
+                const T v = to_store_d<T>((double)x[j]);
+                if (!isfinite(x[j])) bad = true;
                 A[i + (c0 + j) * lda] = v;
                 lt[j] = v;
             }
@@ -136,8 +136,8 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
             }
 #pragma unroll
             for (int k = 0; k < L; ++k) {
-                if (!isfinite((float)y[k])) bad = true;
-                col[k] = to_store<T>((float)y[k]);
+                if (!isfinite(y[k])) bad = true;
+                col[k] = to_store_d<T>((double)y[k]);
             }
         }
     }
@@ -297,8 +297,12 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
 
 // ========================================== Schur GEMM, FP32/FP64 matrix cores
 template <typename T> struct mfma16x4;
+// Output layout of the 16x16 fragment: lane l holds column l & 15; register q
+// holds row 4 (l >> 4) + q for the FP32 instruction and row (l >> 4) + 4 q for
+// the FP64 one (checked on gfx950 with an in-bounds probe).
 template <> struct mfma16x4<float> {
     typedef f32x4 acc_t;
+    static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
     static __device__ __forceinline__ acc_t op(float a, float b, acc_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -306,6 +310,7 @@ template <> struct mfma16x4<float> {
 };
 template <> struct mfma16x4<double> {
     typedef f64x4 acc_t;
+    static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
     static __device__ __forceinline__ acc_t op(double a, double b, acc_t c)
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -373,10 +378,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma4(int M, int N, int K, const T
 #pragma unroll
         for (int fn = 0; fn < 2; ++fn) {
             const int col = col0 + wn * 32 + fn * 16 + (lane & 15);
-            const int rb0 = row0 + wm * 32 + fm * 16 + (lane >> 4) * 4;
+            const int rb0 = row0 + wm * 32 + fm * 16;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                T *p = C + (int64_t)col * ldc + rb0 + q;
+                T *p = C + (int64_t)col * ldc + rb0 + mfma16x4<T>::row(lane, q);
                 const T v = *p - acc[fm][fn][q];
                 bad |= !isfinite((double)v);
                 *p = v;
@@ -570,8 +575,8 @@ __global__ __launch_bounds__(PP_THREADS) void k_pivot_panel(int64_t Np, int64_t 
     bool bad = false;
     for (int64_t e = tid; e < m * L; e += PP_THREADS) {
         const int64_t i = e % m, j = e / m;
-        const T v = to_store<T>((float)S[e]);
-        if (!isfinite((float)S[e])) bad = true;
+        const T v = to_store_d<T>((double)S[e]);
+        if (!isfinite(S[e])) bad = true;
         A[(c0 + i) + (c0 + j) * lda] = v;
         if (i >= L) LT[(c0 + i) * (int64_t)NB_OUT + (c0 - k0) + j] = v;
     }
@@ -627,8 +632,8 @@ __global__ __launch_bounds__(256) void k_u12(int64_t Np, int64_t c0, T *__restri
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        if (!isfinite((float)y[k])) bad = true;
-        col[k] = to_store<T>((float)y[k]);
+        if (!isfinite(y[k])) bad = true;
+        col[k] = to_store_d<T>((double)y[k]);
     }
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
 }
@@ -639,7 +644,7 @@ __global__ __launch_bounds__(256) void k_check_finite(int64_t Np, const T *__res
 {
     const int64_t j = blockIdx.x;
     bool bad = false;
-    for (int64_t i = threadIdx.x; i < Np; i += 256) bad |= !isfinite((float)to_f32(A[i + j * lda]));
+    for (int64_t i = threadIdx.x; i < Np; i += 256) bad |= !isfinite((double)to_f32(A[i + j * lda]));
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
 }
 

@@ -96,16 +96,23 @@ def test_getrf_fp64_pivoting_path(env, n):
     np.testing.assert_allclose(from_cm(T), LU_ref, rtol=1e-9, atol=1e-9 * np.abs(LU_ref).max())
 
 
-def check_backward_error(A_in, LU, ipiv, u, nstages):
-    """|P A - L U| <= k u (|P A| + |L| |U|) elementwise, with |L| <= 1."""
+def check_backward_error(A_in, LU, ipiv, u, nstages, u_acc, eta_sub):
+    """Componentwise backward error of the stored factors, |L| <= 1.
+
+    |P A - L U| <= (k + 2) (u (|P A| + |L| |U|) + eta_sub) + n u_acc |L| |U|:
+    k roundings to the storage precision (relative u, or absolute eta_sub for
+    subnormal results) plus the accumulation error of inner products of
+    length <= n carried in the accumulation precision u_acc.
+    """
     n = A_in.shape[0]
     L = np.tril(LU, -1) + np.eye(n)
     U = np.triu(LU)
     p = O.perm_from_ipiv(ipiv)
     PA = A_in[p]
     assert np.abs(np.tril(LU, -1)).max() <= 1.0 + 4 * u
+    LUabs = np.abs(L) @ np.abs(U)
     err = np.abs(PA - L @ U)
-    bound = (nstages + 2) * u * (np.abs(PA) + np.abs(L) @ np.abs(U))
+    bound = (nstages + 2) * (u * (np.abs(PA) + LUabs) + eta_sub) + n * u_acc * LUabs
     ratio = (err / np.maximum(bound, 1e-300)).max()
     assert ratio <= 1.0, ratio
 
@@ -131,7 +138,8 @@ def test_getrf_low_precision_backward_error(env, prec, u, kind, n):
     if kind != "gaussian":
         assert np.array_equal(piv, np.arange(n))  # no interchange is ever the max
     stages = (n + 511) // 512 + 8
-    check_backward_error(A_in, from_cm(T), piv, u, stages)
+    eta_sub = {"fp16": 2.0 ** -25, "bf16": 2.0 ** -134, "fp32": 2.0 ** -150}[prec]
+    check_backward_error(A_in, from_cm(T), piv, u, stages, U32, eta_sub)
 
 
 def test_getrf_singular_reports_info(env):

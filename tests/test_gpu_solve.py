@@ -53,7 +53,8 @@ def test_heq_solve_matches_oracle(env, n, c, prec, solver):
     assert rep.its in (ref.its, ref.its + 1)
     assert rel_err(xg, ref.x_floor) <= 1e-9
     # the early history tracks FP64 Newton (eq. (2.13)); BF16's eta_J is larger
-    k = min(3, rep.its)
+    # compare the history above the FP64 rounding floor (~1e-13 relative)
+    k = min(3, rep.its, int(np.sum(ref.rel_hist[1:] > 1e-12)))
     rtol = 5e-2 if prec == "BF16" else 2e-3
     np.testing.assert_allclose(rep.resid_rel[1:k + 1], ref.rel_hist[1:k + 1], rtol=rtol)
     assert not any(rep.pivoted)
