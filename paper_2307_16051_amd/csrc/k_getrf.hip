@@ -29,116 +29,258 @@
 
 namespace n3p {
 
+// One phase of the in-register 64x64 LU (no interchange, pivot check): the
+// live columns k0 .. k0+W-1 of row r are v[0 .. W-1].  Four groups of four
+// columns are eliminated; after each group the finished columns are stored to
+// `out` (row r of the block) and the live part rotates left by four.
+template <typename CT, int W>
+__device__ __forceinline__ void leaf_lu_phase(CT (&v)[NB_LEAF], int r, int k0, CT margin,
+                                              bool &fail, CT *out)
+{
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            const int k = k0 + 4 * g + kq;  // v[kq] holds column k
+            const CT piv = lane_bcast(v[kq], k);
+            if (!(fabs(piv) > (CT)0)) fail = true;
+            if (r > k) {
+                if (!(fabs(v[kq]) <= margin * fabs(piv))) fail = true;
+                v[kq] = v[kq] / piv;
+            }
+            const CT l = r > k ? v[kq] : (CT)0;
+#pragma unroll
+            for (int j = kq + 1; j < W; ++j) v[j] -= l * lane_bcast(v[j], k);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[k0 + 4 * g + j] = v[j];
+#pragma unroll
+        for (int j = 0; j < W - 4; ++j) v[j] = v[j + 4];
+    }
+}
+
 // =========================================================== leaf (no-swap)
-// Block b < nrt: 256 rows of L21 below the leaf; b >= nrt: 256 columns of the
-// U row block to the right of the leaf.  Every block first factors the 64x64
-// diagonal block itself (identical arithmetic in every block), so no block
-// waits for another.  The factored diagonal block goes to DG (a side buffer):
-// blocks still reading the unfactored block from A must not see it change.
-// DGprev (if non-null) is the previous leaf's diagonal block, copied into A
-// by block 0 here (nothing else touches that region during this kernel).
+// Blocks b < nrt: 64 rows of L21 below the leaf; nrt <= b < nrt + nct: 64
+// columns of the U row block to the right of the leaf (when the leaf is the
+// last one, a single block only stores the diagonal block).  Every block first
+// factors the 64x64 diagonal block itself (identical arithmetic in every
+// block), so no block waits for another.  The factored diagonal block goes to
+// DG (a side buffer): blocks still reading the unfactored block from A must
+// not see it change.  DGprev (if non-null) is the previous leaf's diagonal
+// block, copied into A by block 0 (nothing else touches that region now).
+//
+// Code size matters here: every step runs once per block, so the loops over
+// columns run in groups of four (the group index is a runtime loop, the four
+// steps inside are unrolled) and the per-thread register arrays are rotated
+// by one after each group, which keeps every register index static.
 template <typename T>
 __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__restrict__ A,
                                                    int64_t lda, T *__restrict__ LT, int64_t k0,
-                                                   int nrt, T *__restrict__ DG,
+                                                   int nrt, int nct, T *__restrict__ DG,
                                                    const T *__restrict__ DGprev, int64_t cprev,
                                                    int *__restrict__ flags)
 {
     typedef typename compute_of<T>::type CT;
     constexpr int L = NB_LEAF;
-    __shared__ CT Dm[L][L + 1];
+    constexpr int LP = L + 4;
+    __shared__ __attribute__((aligned(16))) CT Dm[L][LP];     // factored diagonal block
+    // Ui[k][q][c] = U[k][4c+q] and Li[k][q][u] = L[4u+q][k] where that column
+    // (row) index exceeds k, else 0.  Flat, with 16 trailing entries so that
+    // reads for register slots past column 63 stay inside the array (those
+    // slots are dead: they are rotated out without ever being stored).
+    __shared__ __attribute__((aligned(16))) CT Ui[L * L + 16];
+    __shared__ __attribute__((aligned(16))) CT Li[L * L + 16];
+    __shared__ __attribute__((aligned(16))) CT Sg[L][LP];     // staging of one 64x64 tile
+    __shared__ CT rdiag[L];
     __shared__ int sfail;
     if (block_flag(&flags[FLAG_FAIL])) return;
     const int t = threadIdx.x;
-    if (blockIdx.x == 0 && DGprev) {
+    const int bid = blockIdx.x;
+    if (bid == 0 && DGprev) {
         for (int e = t; e < L * L; e += 256) {
             const int i = e % L, j = e / L;
             A[(cprev + i) + (cprev + j) * lda] = DGprev[i + j * L];
         }
     }
     if (t == 0) sfail = 0;
-    for (int e = t; e < L * L; e += 256) {
-        const int i = e % L, j = e / L;
-        Dm[i][j] = (CT)to_f32(A[(c0 + i) + (c0 + j) * lda]);
+    constexpr int CH = 16 / (int)sizeof(T);  // elements per 16-byte chunk
+    union Chunk { uint4 v; T e[CH]; };
+    for (int e = t; e < L * L / CH; e += 256) {  // diagonal block, column chunks
+        const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
+        Chunk ch;
+        ch.v = *(const uint4 *)(A + (c0 + i0) + (c0 + j) * lda);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) Dm[i0 + u][j] = (CT)to_f32(ch.e[u]);
     }
     __syncthreads();
     const CT margin = (CT)(1.0 - 1.0 / 256.0);
-    const int r = t % L, g = t / L;
-    bool fail = false;
-    for (int k = 0; k < L; ++k) {
-        const CT piv = Dm[k][k];
-        CT l = 0;
-        if (!(fabs(piv) > (CT)0)) fail = true;
-        if (r > k) {
-            const CT a = Dm[r][k];
-            if (!(fabs(a) <= margin * fabs(piv))) fail = true;
-            l = a / piv;
-        }
-        __syncthreads();
-        if (r > k) {
-            if (g == 0) Dm[r][k] = l;
-            for (int j = k + 1 + g; j < L; j += 4) Dm[r][j] -= l * Dm[k][j];
-        }
-        __syncthreads();
+    // ---- diagonal block, no interchange, with the partial-pivoting check.
+    // One wavefront factors it with no barrier or LDS access per step: lane r
+    // keeps row r in registers and reads the pivot row from lane k with
+    // v_readlane.  Columns are processed in groups of four inside four phases
+    // whose live width shrinks (64, 48, 32, 16 columns); within a phase the
+    // row is rotated left by four after each group, so every register index
+    // is static and the loop body is reused.
+    if (t < 64) {
+        const int r = t;
+        CT v[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j) v[j] = Dm[r][j];
+        bool fail = false;
+        leaf_lu_phase<CT, 64>(v, r, 0, margin, fail, &Dm[r][0]);
+        leaf_lu_phase<CT, 48>(v, r, 16, margin, fail, &Dm[r][0]);
+        leaf_lu_phase<CT, 32>(v, r, 32, margin, fail, &Dm[r][0]);
+        leaf_lu_phase<CT, 16>(v, r, 48, margin, fail, &Dm[r][0]);
+        if (fail) sfail = 1;
     }
-    if (fail) sfail = 1;
     __syncthreads();
-    if (sfail) {
+    if (sfail) {  // block-uniform: settled before the barrier
         if (t == 0) set_flag(&flags[FLAG_FAIL], 1);
         return;
     }
-    if (blockIdx.x == 0) {
+    for (int e = t; e < L * L + 16; e += 256) {
+        const int k = e / L, m = e % L;
+        const int q = m / 16, c = m % 16, j = 4 * c + q;
+        const bool in = e < L * L && j > k;
+        Ui[e] = in ? Dm[k][j] : (CT)0;
+        Li[e] = in ? Dm[j][k] : (CT)0;
+    }
+    if (t < L) rdiag[t] = (CT)1 / Dm[t][t];
+    if (bid == 0) {
         for (int e = t; e < L * L; e += 256) {
             const int i = e % L, j = e / L;
             DG[i + j * L] = to_store_d<T>((double)Dm[i][j]);
         }
     }
-    bool bad = false;
-    if ((int)blockIdx.x < nrt) {
-        // L21 row i: solve l U11 = a (row vector), checking each candidate
-        const int64_t i = c0 + L + (int64_t)blockIdx.x * 256 + t;
-        if (i < Np) {
-            CT x[L];
+    __syncthreads();
+    const int q = t % 4, w4 = t / 4;  // lane-in-quad, quad index
+    bool bad = false, fail = false;
+    if (bid < nrt) {
+        // ---- L21 rows [R0, R0+64): l U11 = a.  Quad w4 owns row R0 + w4; lane q
+        // holds columns 4(c + kc) + q.  At step k the owner lane holds the
+        // Schur complement entry partial pivoting would compare: it checks it
+        // against the pivot, scales it and broadcasts it to its quad.
+        const int64_t R0 = c0 + L + (int64_t)bid * L;
+        for (int e = t; e < L * L / CH; e += 256) {  // coalesced: column chunks
+            const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
+            Chunk ch;
+            ch.v = *(const uint4 *)(A + (R0 + i0) + (c0 + j) * lda);
 #pragma unroll
-            for (int j = 0; j < L; ++j) x[j] = (CT)to_f32(A[i + (c0 + j) * lda]);
+            for (int u = 0; u < CH; ++u) Sg[i0 + u][j] = (CT)to_f32(ch.e[u]);
+        }
+        __syncthreads();
+        CT x[16];
 #pragma unroll
-            for (int j = 0; j < L; ++j) {
-                CT s = x[j];
+        for (int c = 0; c < 16; ++c) x[c] = Sg[w4][4 * c + q];
+        // this group's four U rows (lane-in-quad slice) in registers, the next
+        // group's loaded while the current one is eliminated
+        CT ucur[4][16], unxt[4][16];
 #pragma unroll
-                for (int k = 0; k < j; ++k) s -= x[k] * Dm[k][j];
-                if (!(fabs(s) <= margin * fabs(Dm[j][j]))) fail = true;
-                x[j] = s / Dm[j][j];
+        for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) ucur[kq][c] = Ui[kq * L + q * 16 + c];
+        for (int kc = 0; kc < 16; ++kc) {
+            if (kc + 1 < 16) {
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+                    for (int c = 0; c < 16; ++c)
+                        unxt[kq][c] = Ui[(4 * (kc + 1) + kq) * L + q * 16 + (kc + 1) + c];
             }
-            T *lt = LT + i * (int64_t)NB_OUT + (c0 - k0);
 #pragma unroll
-            for (int j = 0; j < L; ++j) {
-                const T v = to_store_d<T>((double)x[j]);
-                if (!isfinite(x[j])) bad = true;
-                A[i + (c0 + j) * lda] = v;
-                lt[j] = v;
+            for (int kq = 0; kq < 4; ++kq) {
+                const int k = 4 * kc + kq;
+                if (q == kq) {
+                    if (!(fabs(x[0]) <= margin * fabs(Dm[k][k]))) fail = true;
+                    x[0] *= rdiag[k];
+                }
+                const CT xk = kq == 0 ? quad_bcast<0>(x[0]) : kq == 1 ? quad_bcast<1>(x[0])
+                            : kq == 2 ? quad_bcast<2>(x[0]) : quad_bcast<3>(x[0]);
+#pragma unroll
+                for (int c = 0; c < 16; ++c) x[c] -= xk * ucur[kq][c];
             }
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+                for (int c = 0; c < 16; ++c) ucur[kq][c] = unxt[kq][c];
+            Sg[w4][4 * kc + q] = x[0];
+#pragma unroll
+            for (int c = 0; c < 15; ++c) x[c] = x[c + 1];
+            x[15] = 0;
+        }
+        __syncthreads();
+        for (int e = t; e < L * L / CH; e += 256) {  // A: column chunks
+            const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
+            Chunk ch;
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                bad |= !isfinite(Sg[i0 + u][j]);
+                ch.e[u] = to_store_d<T>((double)Sg[i0 + u][j]);
+            }
+            *(uint4 *)(A + (R0 + i0) + (c0 + j) * lda) = ch.v;
+        }
+        for (int e = t; e < L * L / CH; e += 256) {  // LT: row chunks (K contiguous)
+            const int i = e / (L / CH), j0 = (e % (L / CH)) * CH;
+            Chunk ch;
+#pragma unroll
+            for (int u = 0; u < CH; ++u) ch.e[u] = to_store_d<T>((double)Sg[i][j0 + u]);
+            *(uint4 *)(LT + (R0 + i) * (int64_t)NB_OUT + (c0 - k0) + j0) = ch.v;
         }
         if (fail) set_flag(&flags[FLAG_FAIL], 1);
-    } else {
-        // U12 column jc: forward substitution with the unit lower L11
-        const int64_t jc = c0 + L + (int64_t)(blockIdx.x - nrt) * 256 + t;
-        if (jc < Np) {
-            T *col = A + jc * lda + c0;
-            CT y[L];
+    } else if (bid - nrt < nct) {
+        // ---- U12 columns [C0, C0+64): forward substitution with the unit
+        // lower L11.  Quad w4 owns column C0 + w4; lane q holds rows
+        // 4(u + ku) + q of the current group ku.
+        const int64_t C0 = c0 + L + (int64_t)(bid - nrt) * L;
+        for (int e = t; e < L * L / CH; e += 256) {
+            const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
+            Chunk ch;
+            ch.v = *(const uint4 *)(A + (c0 + i0) + (C0 + j) * lda);
 #pragma unroll
-            for (int k = 0; k < L; ++k) y[k] = (CT)to_f32(col[k]);
+            for (int u = 0; u < CH; ++u) Sg[i0 + u][j] = (CT)to_f32(ch.e[u]);
+        }
+        __syncthreads();
+        CT y[16];
 #pragma unroll
-            for (int k = 1; k < L; ++k) {
-                CT s = y[k];
+        for (int u = 0; u < 16; ++u) y[u] = Sg[4 * u + q][w4];
+        CT lcur[4][16], lnxt[4][16];
 #pragma unroll
-                for (int m = 0; m < k; ++m) s -= Dm[k][m] * y[m];
-                y[k] = s;
+        for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) lcur[kq][u] = Li[kq * L + q * 16 + u];
+        for (int ku = 0; ku < 16; ++ku) {
+            if (ku + 1 < 16) {
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        lnxt[kq][u] = Li[(4 * (ku + 1) + kq) * L + q * 16 + (ku + 1) + u];
             }
 #pragma unroll
-            for (int k = 0; k < L; ++k) {
-                if (!isfinite(y[k])) bad = true;
-                col[k] = to_store_d<T>((double)y[k]);
+            for (int kq = 0; kq < 4; ++kq) {
+                const CT yk = kq == 0 ? quad_bcast<0>(y[0]) : kq == 1 ? quad_bcast<1>(y[0])
+                            : kq == 2 ? quad_bcast<2>(y[0]) : quad_bcast<3>(y[0]);
+#pragma unroll
+                for (int u = 0; u < 16; ++u) y[u] -= lcur[kq][u] * yk;
             }
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+                for (int u = 0; u < 16; ++u) lcur[kq][u] = lnxt[kq][u];
+            Sg[4 * ku + q][w4] = y[0];
+#pragma unroll
+            for (int u = 0; u < 15; ++u) y[u] = y[u + 1];
+            y[15] = 0;
+        }
+        __syncthreads();
+        for (int e = t; e < L * L / CH; e += 256) {
+            const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
+            Chunk ch;
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                bad |= !isfinite(Sg[i0 + u][j]);
+                ch.e[u] = to_store_d<T>((double)Sg[i0 + u][j]);
+            }
+            *(uint4 *)(A + (c0 + i0) + (C0 + j) * lda) = ch.v;
         }
     }
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
@@ -654,12 +796,12 @@ static hipError_t leaf_spec_t(int64_t Np, int64_t c0, void *A, int64_t lda, void
                               void *DG, const void *DGprev, int64_t cprev, int *flags,
                               hipStream_t s)
 {
-    const int64_t below = Np - c0 - NB_LEAF;
-    const int nrt = (int)((below + 255) / 256);
+    const int64_t below = Np - c0 - NB_LEAF;  // a multiple of NB_LEAF
+    const int nrt = (int)(below / NB_LEAF);
     const int nct = nrt;
     const unsigned grid = (unsigned)std::max(1, nrt + nct);
     hipLaunchKernelGGL(k_leaf_spec<T>, dim3(grid), dim3(256), 0, s, Np, c0, (T *)A, lda, (T *)LT,
-                       k0, nrt, (T *)DG, (const T *)DGprev, cprev, flags);
+                       k0, nrt, nct, (T *)DG, (const T *)DGprev, cprev, flags);
     return hipGetLastError();
 }
 

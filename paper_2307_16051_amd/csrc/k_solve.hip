@@ -34,9 +34,132 @@ __device__ __forceinline__ bool wait_epoch(int *f, uint32_t epoch, int *flags)
 
 template <typename V> __device__ __forceinline__ V shfl_v(V v, int src) { return __shfl(v, src); }
 
+// Solution values are published as 64-bit words (epoch << 32 | 32 bits of
+// data): FP32 values take one word, FP64 values two.  A reader polls the words
+// it needs until their tag equals the launch's epoch, so the value arrives in
+// the same memory round trip as its readiness (no separate flag), and no
+// cache-wide fence is needed: the words are written and read with
+// agent-scope (coherent) atomic accesses.
+template <typename V> struct tagged;
+template <> struct tagged<float> {
+    static constexpr int W = 1;
+    static __device__ __forceinline__ void put(uint64_t *t, int64_t i, float v, uint32_t ep)
+    {
+        const uint64_t w = ((uint64_t)ep << 32) | (uint32_t)__float_as_uint(v);
+        __hip_atomic_store(&t[i], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    static __device__ __forceinline__ float get(const uint64_t *t, int64_t i, uint32_t ep, int *spins,
+                                                int *flags)
+    {
+        uint64_t w = __hip_atomic_load(&t[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while ((uint32_t)(w >> 32) != ep) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++*spins > SPIN_LIMIT) { set_flag(&flags[FLAG_TIMEOUT], 1); break; }
+            w = __hip_atomic_load(&t[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return __uint_as_float((uint32_t)w);
+    }
+};
+template <> struct tagged<double> {
+    static constexpr int W = 2;
+    static __device__ __forceinline__ void put(uint64_t *t, int64_t i, double v, uint32_t ep)
+    {
+        const uint64_t b = (uint64_t)__double_as_longlong(v);
+        __hip_atomic_store(&t[2 * i], ((uint64_t)ep << 32) | (b & 0xffffffffULL), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&t[2 * i + 1], ((uint64_t)ep << 32) | (b >> 32), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    static __device__ __forceinline__ double get(const uint64_t *t, int64_t i, uint32_t ep, int *spins,
+                                                 int *flags)
+    {
+        uint32_t part[2];
+        for (int h = 0; h < 2; ++h) {
+            uint64_t w = __hip_atomic_load(&t[2 * i + h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while ((uint32_t)(w >> 32) != ep) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++*spins > SPIN_LIMIT) { set_flag(&flags[FLAG_TIMEOUT], 1); break; }
+                w = __hip_atomic_load(&t[2 * i + h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            part[h] = (uint32_t)w;
+        }
+        return __longlong_as_double((long long)(((uint64_t)part[1] << 32) | part[0]));
+    }
+};
+
+// sync layout: int ticket at [0]; tagged words (uint64) from byte offset 16
+__device__ __forceinline__ uint64_t *tag_words(int *sync) { return (uint64_t *)(sync + 4); }
+
+// One published value per lane: lane c of a wavefront fetches the word(s) of
+// column c of a tile, re-polls until every lane's tag matches, and then the
+// values are broadcast lane by lane (v_readlane) into the row updates.
+template <typename V>
+struct lane_word {
+    uint64_t w[tagged<V>::W];
+    __device__ __forceinline__ void issue(const uint64_t *t, int64_t idx, bool valid)
+    {
+#pragma unroll
+        for (int h = 0; h < tagged<V>::W; ++h)
+            w[h] = valid ? __hip_atomic_load(&t[idx * tagged<V>::W + h], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                         : 0;
+    }
+    __device__ __forceinline__ void settle(const uint64_t *t, int64_t idx, bool valid, uint32_t ep,
+                                           int *spins, int *flags)
+    {
+        for (;;) {
+            bool ok = true;
+            if (valid) {
+#pragma unroll
+                for (int h = 0; h < tagged<V>::W; ++h) ok &= (uint32_t)(w[h] >> 32) == ep;
+            }
+            if (__all(ok)) return;
+            __builtin_amdgcn_s_sleep(1);
+            if (++*spins > SPIN_LIMIT) {
+                set_flag(&flags[FLAG_TIMEOUT], 1);
+                return;
+            }
+            if (!ok) issue(t, idx, valid);
+        }
+    }
+    __device__ __forceinline__ V value() const
+    {
+        if constexpr (tagged<V>::W == 1) {
+            return __uint_as_float((uint32_t)w[0]);
+        } else {
+            const uint64_t lo = (uint32_t)w[0], hi = (uint32_t)w[1];
+            return __longlong_as_double((long long)((hi << 32) | lo));
+        }
+    }
+};
+
+// Row update with one published tile: acc += sum_c F[row][c0 + c] y[c0 + c].
+// fv holds the factor entries of this lane's row, yw lane c's published value.
+template <typename V, int BS>
+__device__ __forceinline__ void tile_fma(V &acc, const V (&fv)[BS], const V yv)
+{
+#pragma unroll
+    for (int c = 0; c < BS; ++c) acc += fv[c] * lane_bcast(yv, c);
+}
+
+template <typename T, typename V, int BS>
+__device__ __forceinline__ void load_tile_row(V (&fv)[BS], const T *__restrict__ LU, int64_t lda,
+                                              int64_t rowc, int64_t c0, int64_t n)
+{
+    // unconditional loads (column index clamped in bounds) so that all BS
+    // loads issue back to back; entries past column n-1 are zeroed after
+    T raw[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) raw[c] = LU[rowc + std::min<int64_t>(c0 + c, n - 1) * lda];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) fv[c] = c0 + c < n ? (V)to_f32(raw[c]) : (V)0;
+}
+
 // ---------------------------------------------------------------- lower
 // y = L^{-1} (P b): L unit lower (below the diagonal of LU), perm[i] = the
-// original row placed at position i (null = identity).
+// original row placed at position i (null = identity).  Block `blk` owns rows
+// [blk*BS, blk*BS + BS) (lane = row); wavefront w consumes tiles w, w+4, ...,
+// keeping the next tile's loads in flight while it consumes the current one.
 template <typename T, typename V, int BS>
 __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restrict__ LU, int64_t lda,
                                                     const int32_t *__restrict__ perm,
@@ -44,133 +167,136 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
                                                     int *__restrict__ sync, uint32_t epoch,
                                                     int *__restrict__ flags)
 {
+    static_assert(BS == 64, "a wavefront spans one tile");
     __shared__ int s_blk;
-    __shared__ V ysh[BS];
+    __shared__ V Dg[BS][BS + 1];
     __shared__ V part[4][BS];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) s_blk = __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int blk = s_blk;
+    uint64_t *tags = tag_words(sync);
     const int64_t r0 = (int64_t)blk * BS;
-    const int r = tid % BS, g = tid / BS;
-    const int64_t row = r0 + r;
-    const bool rv = row < n;
-    V acc = 0;
-    for (int jb = 0; jb < blk; ++jb) {
-        if (tid == 0) wait_epoch(&sync[1 + jb], epoch, flags);
-        __syncthreads();
-        __hip_atomic_load(&sync[1 + jb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (tid < BS) ysh[tid] = __hip_atomic_load(&y[(int64_t)jb * BS + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        if (rv) {
-            const T *lp = LU + row + (int64_t)jb * BS * lda;
-#pragma unroll 4
-            for (int c = g; c < BS; c += 4) acc += (V)to_f32(lp[(int64_t)c * lda]) * ysh[c];
-        }
-        __syncthreads();
+    for (int e = tid; e < BS * BS; e += 256) {
+        const int i = e % BS, j = e / BS;
+        Dg[i][j] = (j < i && r0 + i < n) ? (V)to_f32(LU[(r0 + i) + (r0 + j) * lda]) : (V)0;
     }
-    part[g][r] = acc;
+    const int64_t row = r0 + lane;
+    const bool rv = row < n;
+    const int64_t rowc = rv ? row : 0;
+    V acc = 0;
+    int spins = 0;
+    V fv[BS], fvn[BS];
+    lane_word<V> cur, nxt;
+    int jb = wv;
+    if (jb < blk) {
+        load_tile_row<T, V, BS>(fv, LU, lda, rowc, (int64_t)jb * BS, n);
+        cur.issue(tags, (int64_t)jb * BS + lane, true);
+    }
+    for (; jb < blk; jb += 4) {
+        const int nj = jb + 4;
+        if (nj < blk) {
+            load_tile_row<T, V, BS>(fvn, LU, lda, rowc, (int64_t)nj * BS, n);
+            nxt.issue(tags, (int64_t)nj * BS + lane, true);
+        }
+        cur.settle(tags, (int64_t)jb * BS + lane, true, epoch, &spins, flags);
+        tile_fma<V, BS>(acc, fv, cur.value());
+#pragma unroll
+        for (int c = 0; c < BS; ++c) fv[c] = fvn[c];
+        cur = nxt;
+    }
+    part[wv][lane] = acc;
     __syncthreads();
-    if (tid < 64) {
-        // one wavefront: lane r owns row r0 + r (BS == 64)
+    if (wv == 0) {
         V z = 0;
         if (rv) {
             const int64_t src = perm ? (int64_t)perm[row] : row;
-            z = b[src] - (part[0][r] + part[1][r] + part[2][r] + part[3][r]);
-        }
-        V ld[BS];
-#pragma unroll
-        for (int c = 0; c < BS; ++c) {
-            const int64_t col = r0 + c;
-            ld[c] = (rv && col < n && c < r) ? (V)to_f32(LU[row + col * lda]) : (V)0;
+            z = b[src] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
         }
 #pragma unroll
-        for (int c = 0; c < BS; ++c) {
-            const V yc = shfl_v(z, c);
-            if (r > c) z -= ld[c] * yc;
+        for (int c = 0; c < BS; ++c) z -= Dg[lane][c] * lane_bcast(z, c);
+        if (rv) {
+            y[row] = z;
+            tagged<V>::put(tags, row, z, epoch);
         }
-        if (rv) __hip_atomic_store(&y[row], z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (tid == 0) __hip_atomic_store(&sync[1 + blk], (int)epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 // ---------------------------------------------------------------- upper
 // x = S U^{-1} y with S = diag(colscale) (null = identity).  Blocks run from
-// the last to the first; xs holds the unscaled solution other blocks read.
+// the last to the first; other blocks read the unscaled solution (tagged).
 template <typename T, typename V, int BS>
 __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restrict__ LU, int64_t lda,
                                                     const V *__restrict__ yin,
                                                     const float *__restrict__ colscale,
-                                                    V *__restrict__ x, V *__restrict__ xs,
-                                                    int *__restrict__ sync, uint32_t epoch,
-                                                    int *__restrict__ flags)
+                                                    V *__restrict__ x, int *__restrict__ sync,
+                                                    uint32_t epoch, int *__restrict__ flags)
 {
+    static_assert(BS == 64, "a wavefront spans one tile");
     __shared__ int s_blk;
-    __shared__ V xsh[BS];
+    __shared__ V Dg[BS][BS + 1];
+    __shared__ V rd[BS];
     __shared__ V part[4][BS];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nb = (int)((n + BS - 1) / BS);
     if (tid == 0) s_blk = nb - 1 - __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int blk = s_blk;
+    uint64_t *tags = tag_words(sync);
     const int64_t r0 = (int64_t)blk * BS;
-    const int r = tid % BS, g = tid / BS;
-    const int64_t row = r0 + r;
-    const bool rv = row < n;
-    V acc = 0;
-    for (int jb = nb - 1; jb > blk; --jb) {
-        if (tid == 0) wait_epoch(&sync[1 + jb], epoch, flags);
-        __syncthreads();
-        __hip_atomic_load(&sync[1 + jb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (tid < BS) {
-            const int64_t ix = (int64_t)jb * BS + tid;
-            xsh[tid] = ix < n ? __hip_atomic_load(&xs[ix], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (V)0;
-        }
-        __syncthreads();
-        if (rv) {
-            const int64_t c0 = (int64_t)jb * BS;
-            const int cmax = (int)std::min<int64_t>(BS, n - c0);
-            const T *up = LU + row + c0 * lda;
-#pragma unroll 4
-            for (int c = g; c < cmax; c += 4) acc += (V)to_f32(up[(int64_t)c * lda]) * xsh[c];
-        }
-        __syncthreads();
+    for (int e = tid; e < BS * BS; e += 256) {
+        const int i = e % BS, j = e / BS;
+        const bool in = r0 + i < n && r0 + j < n;
+        const V u = in ? (V)to_f32(LU[(r0 + i) + (r0 + j) * lda]) : (V)0;
+        Dg[i][j] = j > i ? u : (V)0;
+        if (i == j) rd[i] = in ? (V)1 / u : (V)1;
     }
-    part[g][r] = acc;
-    __syncthreads();
-    if (tid < 64) {
-        V z = rv ? yin[row] - (part[0][r] + part[1][r] + part[2][r] + part[3][r]) : (V)0;
-        V ud[BS];
-#pragma unroll
-        for (int c = 0; c < BS; ++c) {
-            const int64_t col = r0 + c;
-            ud[c] = (rv && col < n && c >= r) ? (V)to_f32(LU[row + col * lda]) : (V)0;
+    const int64_t row = r0 + lane;
+    const bool rv = row < n;
+    const int64_t rowc = rv ? row : 0;
+    V acc = 0;
+    int spins = 0;
+    V fv[BS], fvn[BS];
+    lane_word<V> cur, nxt;
+    int jb = nb - 1 - wv;
+    if (jb > blk) {
+        load_tile_row<T, V, BS>(fv, LU, lda, rowc, (int64_t)jb * BS, n);
+        cur.issue(tags, (int64_t)jb * BS + lane, (int64_t)jb * BS + lane < n);
+    }
+    for (; jb > blk; jb -= 4) {
+        const int nj = jb - 4;
+        if (nj > blk) {
+            load_tile_row<T, V, BS>(fvn, LU, lda, rowc, (int64_t)nj * BS, n);
+            nxt.issue(tags, (int64_t)nj * BS + lane, true);
         }
-        const V dii = rv ? ud[0] : (V)1;  // placeholder, replaced below
-        (void)dii;
-        V diag = (V)1;
+        const bool valid = (int64_t)jb * BS + lane < n;
+        cur.settle(tags, (int64_t)jb * BS + lane, valid, epoch, &spins, flags);
+        tile_fma<V, BS>(acc, fv, valid ? cur.value() : (V)0);
 #pragma unroll
-        for (int c = 0; c < BS; ++c)
-            if (c == r && rv) diag = ud[c];
+        for (int c = 0; c < BS; ++c) fv[c] = fvn[c];
+        cur = nxt;
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0) {
+        V z = rv ? yin[row] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) : (V)0;
+        const V rdl = rd[lane];
 #pragma unroll
         for (int c = BS - 1; c >= 0; --c) {
-            if (r == c) z = z / diag;
-            const V xc = shfl_v(z, c);
-            if (r < c) z -= ud[c] * xc;
+            if (lane == c) z *= rdl;
+            z -= Dg[lane][c] * lane_bcast(z, c);
         }
         if (rv) {
-            __hip_atomic_store(&xs[row], z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tagged<V>::put(tags, row, z, epoch);
             x[row] = colscale ? z * (V)colscale[row] : z;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (tid == 0) __hip_atomic_store(&sync[1 + blk], (int)epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 __global__ void k_zero_ticket(int *sync) { sync[0] = 0; }
 
-size_t trsv_sync_ints(int64_t n) { return (size_t)(2 + (n + TRSV_BS - 1) / TRSV_BS); }
+// ticket (4 ints, keeps the tag words 16-byte aligned) + 2 tag words per entry
+size_t trsv_sync_ints(int64_t n) { return (size_t)(4 + 4 * n); }
 
 template <typename T, typename V>
 static hipError_t trsv_lower_t(int64_t n, const void *LU, int64_t lda, const int32_t *perm,
@@ -186,13 +312,13 @@ static hipError_t trsv_lower_t(int64_t n, const void *LU, int64_t lda, const int
 
 template <typename T, typename V>
 static hipError_t trsv_upper_t(int64_t n, const void *LU, int64_t lda, const V *y,
-                               const float *colscale, V *x, V *xs, int *sync, uint32_t epoch,
-                               int *flags, hipStream_t s)
+                               const float *colscale, V *x, int *sync, uint32_t epoch, int *flags,
+                               hipStream_t s)
 {
     const unsigned nb = (unsigned)((n + TRSV_BS - 1) / TRSV_BS);
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(1), 0, s, sync);
     hipLaunchKernelGGL((k_trsv_upper<T, V, TRSV_BS>), dim3(nb), dim3(256), 0, s, n, (const T *)LU,
-                       lda, y, colscale, x, xs, sync, epoch, flags);
+                       lda, y, colscale, x, sync, epoch, flags);
     return hipGetLastError();
 }
 
@@ -210,14 +336,14 @@ hipError_t launch_trsv_lower(int prec, int64_t n, const void *LU, int64_t lda, c
 }
 
 hipError_t launch_trsv_upper(int prec, int64_t n, const void *LU, int64_t lda, const float *y,
-                             const float *colscale, float *x, float *yscratch, int *sync,
-                             uint32_t epoch, int *flags, hipStream_t s)
+                             const float *colscale, float *x, int *sync, uint32_t epoch, int *flags,
+                             hipStream_t s)
 {
     switch (prec) {
-    case N3P_FP16: return trsv_upper_t<f16, float>(n, LU, lda, y, colscale, x, yscratch, sync, epoch, flags, s);
-    case N3P_BF16: return trsv_upper_t<bf16, float>(n, LU, lda, y, colscale, x, yscratch, sync, epoch, flags, s);
-    case N3P_FP32: return trsv_upper_t<float, float>(n, LU, lda, y, colscale, x, yscratch, sync, epoch, flags, s);
-    case N3P_FP64: return trsv_upper_t<double, float>(n, LU, lda, y, colscale, x, yscratch, sync, epoch, flags, s);
+    case N3P_FP16: return trsv_upper_t<f16, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s);
+    case N3P_BF16: return trsv_upper_t<bf16, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s);
+    case N3P_FP32: return trsv_upper_t<float, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s);
+    case N3P_FP64: return trsv_upper_t<double, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s);
     }
     return hipErrorInvalidValue;
 }
@@ -230,10 +356,9 @@ hipError_t launch_trsv_lower_f64(int64_t n, const double *LU, int64_t lda, const
 }
 
 hipError_t launch_trsv_upper_f64(int64_t n, const double *LU, int64_t lda, const double *y,
-                                 double *x, double *yscratch, int *sync, uint32_t epoch, int *flags,
-                                 hipStream_t s)
+                                 double *x, int *sync, uint32_t epoch, int *flags, hipStream_t s)
 {
-    return trsv_upper_t<double, double>(n, LU, lda, y, nullptr, x, yscratch, sync, epoch, flags, s);
+    return trsv_upper_t<double, double>(n, LU, lda, y, nullptr, x, sync, epoch, flags, s);
 }
 
 // ---------------------------------------------------------------- matvec

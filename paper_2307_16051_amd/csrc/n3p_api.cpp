@@ -353,7 +353,7 @@ int apply_prec(LinCtx &c, const float *in, float *out)
 {
     HIPCHK(launch_trsv_lower(c.prec, c.n, c.LU, c.ldlu, c.perm, in, c.y, c.sync, c.epoch->next(),
                              c.flags, c.s));
-    HIPCHK(launch_trsv_upper(c.prec, c.n, c.LU, c.ldlu, c.y, c.colscale, out, c.xs, c.sync,
+    HIPCHK(launch_trsv_upper(c.prec, c.n, c.LU, c.ldlu, c.y, c.colscale, out, c.sync,
                              c.epoch->next(), c.flags, c.s));
     return 0;
 }
@@ -735,8 +735,8 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
             HIPCHK(launch_rhs_unit_f64(n, w.Np, w.F, fnd, w.b64, s));
             HIPCHK(launch_trsv_lower_f64(n, (const double *)w.f.A, w.Np, lc.perm, w.b64, w.y64,
                                          w.sync, epoch.next(), w.f.flags, s));
-            HIPCHK(launch_trsv_upper_f64(n, (const double *)w.f.A, w.Np, w.y64, w.x64, w.xs64,
-                                         w.sync, epoch.next(), w.f.flags, s));
+            HIPCHK(launch_trsv_upper_f64(n, (const double *)w.f.A, w.Np, w.y64, w.x64, w.sync,
+                                         epoch.next(), w.f.flags, s));
             lo.sweeps = 1;
             lo.inner = 1;
             HIPCHK(launch_newton_update_f64(n, x, fnd, w.x64, s));
@@ -894,12 +894,12 @@ N3P_API int n3p_getrs(int prec, int64_t n, const void *LU, int64_t lda, const in
         HIPCHK(launch_trsv_lower_f64(n, (const double *)LU, lda, f.perm, (const double *)bc,
                                      (double *)y, sync, 1, f.flags, s));
         HIPCHK(launch_trsv_upper_f64(n, (const double *)LU, lda, (const double *)y, (double *)b,
-                                     (double *)xs, sync, 2, f.flags, s));
+                                     sync, 2, f.flags, s));
     } else {
         HIPCHK(launch_trsv_lower(prec, n, LU, lda, f.perm, (const float *)bc, (float *)y, sync, 1,
                                  f.flags, s));
-        HIPCHK(launch_trsv_upper(prec, n, LU, lda, (const float *)y, nullptr, (float *)b,
-                                 (float *)xs, sync, 2, f.flags, s));
+        HIPCHK(launch_trsv_upper(prec, n, LU, lda, (const float *)y, nullptr, (float *)b, sync, 2,
+                                 f.flags, s));
     }
     int h[NFLAGS];
     CHK(read_flags(f, s, h));

@@ -72,6 +72,32 @@ __device__ __forceinline__ int block_flag(const int *p)
     return v;
 }
 
+// Cross-lane broadcasts on the VALU path (no LDS round trip).
+// lane_bcast: value held by lane `src` of the wavefront (src wave-uniform).
+__device__ __forceinline__ float lane_bcast(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_bcast(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// quad_bcast<K>: value held by lane K of each group of four lanes (DPP quad_perm).
+template <int K> __device__ __forceinline__ float quad_bcast(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), K * 0x55, 0xF, 0xF, false));
+}
+template <int K> __device__ __forceinline__ double quad_bcast(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), K * 0x55, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), K * 0x55, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 inline size_t elem_size(int prec)
@@ -155,14 +181,13 @@ hipError_t launch_trsv_lower(int prec, int64_t n, const void *LU, int64_t lda, c
                              const float *b, float *y, int *sync, uint32_t epoch, int *flags,
                              hipStream_t s);
 hipError_t launch_trsv_upper(int prec, int64_t n, const void *LU, int64_t lda, const float *y,
-                             const float *colscale, float *x, float *yscratch, int *sync,
-                             uint32_t epoch, int *flags, hipStream_t s);
+                             const float *colscale, float *x, int *sync, uint32_t epoch, int *flags,
+                             hipStream_t s);
 hipError_t launch_trsv_lower_f64(int64_t n, const double *LU, int64_t lda, const int32_t *perm,
                                  const double *b, double *y, int *sync, uint32_t epoch,
                                  int *flags, hipStream_t s);
 hipError_t launch_trsv_upper_f64(int64_t n, const double *LU, int64_t lda, const double *y,
-                                 double *x, double *yscratch, int *sync, uint32_t epoch,
-                                 int *flags, hipStream_t s);
+                                 double *x, int *sync, uint32_t epoch, int *flags, hipStream_t s);
 hipError_t launch_gemv_resid(int64_t n, const float *A, int64_t lda, const float *u,
                              const float *b, float *r, double *part, hipStream_t s);
 // y = A v (FP32 out) for GMRES
