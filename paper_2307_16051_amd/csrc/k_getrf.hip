@@ -29,33 +29,26 @@
 
 namespace n3p {
 
-// One phase of the in-register 64x64 LU (no interchange, pivot check): the
-// live columns k0 .. k0+W-1 of row r are v[0 .. W-1].  Four groups of four
-// columns are eliminated; after each group the finished columns are stored to
-// `out` (row r of the block) and the live part rotates left by four.
-template <typename CT, int W>
-__device__ __forceinline__ void leaf_lu_phase(CT (&v)[NB_LEAF], int r, int k0, CT margin,
-                                              bool &fail, CT *out)
+// oct_bcast<K>: value held by lane K of each group of eight lanes.  A quad
+// broadcast gives every quad its own lane K % 4; the quad of the octet that
+// does not hold lane K then takes it from its neighbour quad by a row shift of
+// four lanes, written only to that quad's banks.
+template <int K> __device__ __forceinline__ int oct_bcast_i(int v)
 {
-    for (int g = 0; g < 4; ++g) {
-#pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-            const int k = k0 + 4 * g + kq;  // v[kq] holds column k
-            const CT piv = lane_bcast(v[kq], k);
-            if (!(fabs(piv) > (CT)0)) fail = true;
-            if (r > k) {
-                if (!(fabs(v[kq]) <= margin * fabs(piv))) fail = true;
-                v[kq] = v[kq] / piv;
-            }
-            const CT l = r > k ? v[kq] : (CT)0;
-#pragma unroll
-            for (int j = kq + 1; j < W; ++j) v[j] -= l * lane_bcast(v[j], k);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) out[k0 + 4 * g + j] = v[j];
-#pragma unroll
-        for (int j = 0; j < W - 4; ++j) v[j] = v[j + 4];
-    }
+    const int qb = __builtin_amdgcn_mov_dpp(v, (K & 3) * 0x55, 0xF, 0xF, false);
+    if (K < 4) return __builtin_amdgcn_update_dpp(qb, qb, 0x114, 0xF, 0xA, false);  // row_shr:4
+    return __builtin_amdgcn_update_dpp(qb, qb, 0x104, 0xF, 0x5, false);             // row_shl:4
+}
+template <int K> __device__ __forceinline__ float oct_bcast(float v)
+{
+    return __int_as_float(oct_bcast_i<K>(__float_as_int(v)));
+}
+template <int K> __device__ __forceinline__ double oct_bcast(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = oct_bcast_i<K>((int)(b & 0xffffffffLL));
+    const int hi = oct_bcast_i<K>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // =========================================================== leaf (no-swap)
@@ -68,35 +61,42 @@ __device__ __forceinline__ void leaf_lu_phase(CT (&v)[NB_LEAF], int r, int k0, C
 // not see it change.  DGprev (if non-null) is the previous leaf's diagonal
 // block, copied into A by block 0 (nothing else touches that region now).
 //
-// Code size matters here: every step runs once per block, so the loops over
-// columns run in groups of four (the group index is a runtime loop, the four
-// steps inside are unrolled) and the per-thread register arrays are rotated
-// by one after each group, which keeps every register index static.
+// Every column step is a short dependent chain, so the work is spread over
+// lanes and kept on the VALU path: the diagonal LU uses four lanes per row
+// (pivot row through LDS, multipliers by DPP quad broadcast, one barrier per
+// step); the triangular solves use eight lanes per row or column (DPP8
+// broadcasts, no barrier).  Column loops run in groups whose index is a
+// runtime loop while the steps inside are unrolled; per-lane register arrays
+// rotate after each group so every register index stays static.
+constexpr int LEAF_THREADS = 512;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__restrict__ A,
-                                                   int64_t lda, T *__restrict__ LT, int64_t k0,
-                                                   int nrt, int nct, T *__restrict__ DG,
-                                                   const T *__restrict__ DGprev, int64_t cprev,
-                                                   int *__restrict__ flags)
+__global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t c0, T *__restrict__ A,
+                                                            int64_t lda, T *__restrict__ LT, int64_t k0,
+                                                            int nrt, int nct, T *__restrict__ DG,
+                                                            const T *__restrict__ DGprev, int64_t cprev,
+                                                            int *__restrict__ flags)
 {
     typedef typename compute_of<T>::type CT;
     constexpr int L = NB_LEAF;
     constexpr int LP = L + 4;
-    __shared__ __attribute__((aligned(16))) CT Dm[L][LP];     // factored diagonal block
-    // Ui[k][q][c] = U[k][4c+q] and Li[k][q][u] = L[4u+q][k] where that column
-    // (row) index exceeds k, else 0.  Flat, with 16 trailing entries so that
-    // reads for register slots past column 63 stay inside the array (those
-    // slots are dead: they are rotated out without ever being stored).
-    __shared__ __attribute__((aligned(16))) CT Ui[L * L + 16];
-    __shared__ __attribute__((aligned(16))) CT Li[L * L + 16];
-    __shared__ __attribute__((aligned(16))) CT Sg[L][LP];     // staging of one 64x64 tile
+    constexpr int NT = LEAF_THREADS;
+    __shared__ __attribute__((aligned(16))) CT Dm[L][LP];       // diagonal block
+    // Ui[k][g][c] = U[k][8c+g], Li[k][g][u] = L[8u+g][k] where that index
+    // exceeds k, else 0; flat with 8 trailing entries so reads for register
+    // slots past index 63 stay in the array (those slots are dead).
+    __shared__ __attribute__((aligned(16))) CT Ui[L * L + 8];
+    __shared__ __attribute__((aligned(16))) CT Li[L * L + 8];
+    __shared__ __attribute__((aligned(16))) CT Sg[L][LP];       // staging of one tile
+    __shared__ __attribute__((aligned(16))) CT rowbuf[2][4][16];  // pivot row, by lane
+    __shared__ CT pivbuf[2];                                      // pivot value
     __shared__ CT rdiag[L];
     __shared__ int sfail;
     if (block_flag(&flags[FLAG_FAIL])) return;
     const int t = threadIdx.x;
     const int bid = blockIdx.x;
     if (bid == 0 && DGprev) {
-        for (int e = t; e < L * L; e += 256) {
+        for (int e = t; e < L * L; e += NT) {
             const int i = e % L, j = e / L;
             A[(cprev + i) + (cprev + j) * lda] = DGprev[i + j * L];
         }
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
     if (t == 0) sfail = 0;
     constexpr int CH = 16 / (int)sizeof(T);  // elements per 16-byte chunk
     union Chunk { uint4 v; T e[CH]; };
-    for (int e = t; e < L * L / CH; e += 256) {  // diagonal block, column chunks
+    for (int e = t; e < L * L / CH; e += NT) {  // diagonal block, column chunks
         const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
         Chunk ch;
         ch.v = *(const uint4 *)(A + (c0 + i0) + (c0 + j) * lda);
@@ -114,22 +114,54 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
     __syncthreads();
     const CT margin = (CT)(1.0 - 1.0 / 256.0);
     // ---- diagonal block, no interchange, with the partial-pivoting check.
-    // One wavefront factors it with no barrier or LDS access per step: lane r
-    // keeps row r in registers and reads the pivot row from lane k with
-    // v_readlane.  Columns are processed in groups of four inside four phases
-    // whose live width shrinks (64, 48, 32, 16 columns); within a phase the
-    // row is rotated left by four after each group, so every register index
-    // is static and the loop body is reused.
-    if (t < 64) {
-        const int r = t;
-        CT v[L];
+    // Threads 0..255: quad r (lanes q = 0..3) owns row r; lane q holds
+    // columns 4(kc + c) + q of the current group kc in x[c].  At step k the
+    // quad of row k publishes the row (finished entries as 0) and its pivot;
+    // after one barrier every row below computes its multiplier in the lane
+    // owning column k (lane k % 4, slot 0), checks it, broadcasts it to its
+    // quad and updates its 16 columns.
+    {
+        const bool act = t < 4 * L;
+        const int r = t / 4, q = t % 4;
+        CT x[16];
 #pragma unroll
-        for (int j = 0; j < L; ++j) v[j] = Dm[r][j];
+        for (int c = 0; c < 16; ++c) x[c] = act ? Dm[r][4 * c + q] : (CT)0;
         bool fail = false;
-        leaf_lu_phase<CT, 64>(v, r, 0, margin, fail, &Dm[r][0]);
-        leaf_lu_phase<CT, 48>(v, r, 16, margin, fail, &Dm[r][0]);
-        leaf_lu_phase<CT, 32>(v, r, 32, margin, fail, &Dm[r][0]);
-        leaf_lu_phase<CT, 16>(v, r, 48, margin, fail, &Dm[r][0]);
+        for (int kc = 0; kc < 16; ++kc) {
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) {
+                const int k = 4 * kc + kq, bsel = kq & 1;
+                if (act && r == k) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c)
+                        rowbuf[bsel][q][c] = (c == 0 && q <= kq) ? (CT)0 : x[c];
+                    if (q == kq) {
+                        pivbuf[bsel] = x[0];
+                        if (!(fabs(x[0]) > (CT)0)) fail = true;
+                    }
+                }
+                __syncthreads();
+                const CT piv = pivbuf[bsel];
+                CT l = 0;
+                if (act && q == kq && r > k) {
+                    if (!(fabs(piv) > (CT)0)) fail = true;
+                    if (!(fabs(x[0]) <= margin * fabs(piv))) fail = true;
+                    x[0] = x[0] / piv;
+                    l = x[0];
+                }
+                l = kq == 0 ? quad_bcast<0>(l) : kq == 1 ? quad_bcast<1>(l)
+                  : kq == 2 ? quad_bcast<2>(l) : quad_bcast<3>(l);
+                if (act && r > k) {
+                    const CT *pr = &rowbuf[bsel][q][0];
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) x[c] -= l * pr[c];
+                }
+            }
+            if (act) Dm[r][4 * kc + q] = x[0];  // column 4kc+q of row r is final
+#pragma unroll
+            for (int c = 0; c < 15; ++c) x[c] = x[c + 1];
+            x[15] = 0;
+        }
         if (fail) sfail = 1;
     }
     __syncthreads();
@@ -137,30 +169,31 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
         if (t == 0) set_flag(&flags[FLAG_FAIL], 1);
         return;
     }
-    for (int e = t; e < L * L + 16; e += 256) {
+    for (int e = t; e < L * L + 8; e += NT) {
         const int k = e / L, m = e % L;
-        const int q = m / 16, c = m % 16, j = 4 * c + q;
+        const int g = m / 8, c = m % 8, j = 8 * c + g;
         const bool in = e < L * L && j > k;
         Ui[e] = in ? Dm[k][j] : (CT)0;
         Li[e] = in ? Dm[j][k] : (CT)0;
     }
     if (t < L) rdiag[t] = (CT)1 / Dm[t][t];
     if (bid == 0) {
-        for (int e = t; e < L * L; e += 256) {
+        for (int e = t; e < L * L; e += NT) {
             const int i = e % L, j = e / L;
             DG[i + j * L] = to_store_d<T>((double)Dm[i][j]);
         }
     }
     __syncthreads();
-    const int q = t % 4, w4 = t / 4;  // lane-in-quad, quad index
+    const int g = t % 8, w8 = t / 8;  // lane-in-octet, octet index (row or column)
     bool bad = false, fail = false;
     if (bid < nrt) {
-        // ---- L21 rows [R0, R0+64): l U11 = a.  Quad w4 owns row R0 + w4; lane q
-        // holds columns 4(c + kc) + q.  At step k the owner lane holds the
-        // Schur complement entry partial pivoting would compare: it checks it
-        // against the pivot, scales it and broadcasts it to its quad.
+        // ---- L21 rows [R0, R0+64): l U11 = a.  Octet w8 owns row R0 + w8;
+        // lane g holds columns 8(c + kc) + g of the current group kc.  At step
+        // k the owner lane (g = k % 8, slot 0) holds the Schur complement entry
+        // partial pivoting would compare: it checks it against the pivot,
+        // scales it and broadcasts it to its octet.
         const int64_t R0 = c0 + L + (int64_t)bid * L;
-        for (int e = t; e < L * L / CH; e += 256) {  // coalesced: column chunks
+        for (int e = t; e < L * L / CH; e += NT) {  // coalesced: column chunks
             const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
             Chunk ch;
             ch.v = *(const uint4 *)(A + (R0 + i0) + (c0 + j) * lda);
@@ -168,47 +201,45 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
             for (int u = 0; u < CH; ++u) Sg[i0 + u][j] = (CT)to_f32(ch.e[u]);
         }
         __syncthreads();
-        CT x[16];
+        CT x[8];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) x[c] = Sg[w4][4 * c + q];
-        // this group's four U rows (lane-in-quad slice) in registers, the next
-        // group's loaded while the current one is eliminated
-        CT ucur[4][16], unxt[4][16];
+        for (int c = 0; c < 8; ++c) x[c] = Sg[w8][8 * c + g];
+        for (int kc = 0; kc < 8; ++kc) {
+            CT u[8][8];
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq)
+            for (int kq = 0; kq < 8; ++kq)
 #pragma unroll
-            for (int c = 0; c < 16; ++c) ucur[kq][c] = Ui[kq * L + q * 16 + c];
-        for (int kc = 0; kc < 16; ++kc) {
-            if (kc + 1 < 16) {
+                for (int c = 0; c < 8; ++c) u[kq][c] = Ui[(8 * kc + kq) * L + g * 8 + kc + c];
+            // this lane owns column 8kc + g: its pivot bound and reciprocal
+            const CT lim = margin * fabs(Dm[8 * kc + g][8 * kc + g]);
+            const CT rd = rdiag[8 * kc + g];
 #pragma unroll
-                for (int kq = 0; kq < 4; ++kq)
-#pragma unroll
-                    for (int c = 0; c < 16; ++c)
-                        unxt[kq][c] = Ui[(4 * (kc + 1) + kq) * L + q * 16 + (kc + 1) + c];
-            }
-#pragma unroll
-            for (int kq = 0; kq < 4; ++kq) {
-                const int k = 4 * kc + kq;
-                if (q == kq) {
-                    if (!(fabs(x[0]) <= margin * fabs(Dm[k][k]))) fail = true;
-                    x[0] *= rdiag[k];
+            for (int kq = 0; kq < 8; ++kq) {
+                if (g == kq) {
+                    if (!(fabs(x[0]) <= lim)) fail = true;
+                    x[0] *= rd;
                 }
-                const CT xk = kq == 0 ? quad_bcast<0>(x[0]) : kq == 1 ? quad_bcast<1>(x[0])
-                            : kq == 2 ? quad_bcast<2>(x[0]) : quad_bcast<3>(x[0]);
+                CT xk;
+                switch (kq) {
+                case 0: xk = oct_bcast<0>(x[0]); break;
+                case 1: xk = oct_bcast<1>(x[0]); break;
+                case 2: xk = oct_bcast<2>(x[0]); break;
+                case 3: xk = oct_bcast<3>(x[0]); break;
+                case 4: xk = oct_bcast<4>(x[0]); break;
+                case 5: xk = oct_bcast<5>(x[0]); break;
+                case 6: xk = oct_bcast<6>(x[0]); break;
+                default: xk = oct_bcast<7>(x[0]); break;
+                }
 #pragma unroll
-                for (int c = 0; c < 16; ++c) x[c] -= xk * ucur[kq][c];
+                for (int c = 0; c < 8; ++c) x[c] -= xk * u[kq][c];
             }
+            Sg[w8][8 * kc + g] = x[0];
 #pragma unroll
-            for (int kq = 0; kq < 4; ++kq)
-#pragma unroll
-                for (int c = 0; c < 16; ++c) ucur[kq][c] = unxt[kq][c];
-            Sg[w4][4 * kc + q] = x[0];
-#pragma unroll
-            for (int c = 0; c < 15; ++c) x[c] = x[c + 1];
-            x[15] = 0;
+            for (int c = 0; c < 7; ++c) x[c] = x[c + 1];
+            x[7] = 0;
         }
         __syncthreads();
-        for (int e = t; e < L * L / CH; e += 256) {  // A: column chunks
+        for (int e = t; e < L * L / CH; e += NT) {  // A: column chunks
             const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
             Chunk ch;
 #pragma unroll
@@ -218,7 +249,7 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
             }
             *(uint4 *)(A + (R0 + i0) + (c0 + j) * lda) = ch.v;
         }
-        for (int e = t; e < L * L / CH; e += 256) {  // LT: row chunks (K contiguous)
+        for (int e = t; e < L * L / CH; e += NT) {  // LT: row chunks (K contiguous)
             const int i = e / (L / CH), j0 = (e % (L / CH)) * CH;
             Chunk ch;
 #pragma unroll
@@ -228,10 +259,10 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
         if (fail) set_flag(&flags[FLAG_FAIL], 1);
     } else if (bid - nrt < nct) {
         // ---- U12 columns [C0, C0+64): forward substitution with the unit
-        // lower L11.  Quad w4 owns column C0 + w4; lane q holds rows
-        // 4(u + ku) + q of the current group ku.
+        // lower L11.  Octet w8 owns column C0 + w8; lane g holds rows
+        // 8(u + ku) + g of the current group ku.
         const int64_t C0 = c0 + L + (int64_t)(bid - nrt) * L;
-        for (int e = t; e < L * L / CH; e += 256) {
+        for (int e = t; e < L * L / CH; e += NT) {
             const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
             Chunk ch;
             ch.v = *(const uint4 *)(A + (c0 + i0) + (C0 + j) * lda);
@@ -239,40 +270,38 @@ __global__ __launch_bounds__(256) void k_leaf_spec(int64_t Np, int64_t c0, T *__
             for (int u = 0; u < CH; ++u) Sg[i0 + u][j] = (CT)to_f32(ch.e[u]);
         }
         __syncthreads();
-        CT y[16];
+        CT y[8];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) y[u] = Sg[4 * u + q][w4];
-        CT lcur[4][16], lnxt[4][16];
+        for (int u = 0; u < 8; ++u) y[u] = Sg[8 * u + g][w8];
+        for (int ku = 0; ku < 8; ++ku) {
+            CT lv[8][8];
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq)
+            for (int kq = 0; kq < 8; ++kq)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) lcur[kq][u] = Li[kq * L + q * 16 + u];
-        for (int ku = 0; ku < 16; ++ku) {
-            if (ku + 1 < 16) {
+                for (int u = 0; u < 8; ++u) lv[kq][u] = Li[(8 * ku + kq) * L + g * 8 + ku + u];
 #pragma unroll
-                for (int kq = 0; kq < 4; ++kq)
+            for (int kq = 0; kq < 8; ++kq) {
+                CT yk;
+                switch (kq) {
+                case 0: yk = oct_bcast<0>(y[0]); break;
+                case 1: yk = oct_bcast<1>(y[0]); break;
+                case 2: yk = oct_bcast<2>(y[0]); break;
+                case 3: yk = oct_bcast<3>(y[0]); break;
+                case 4: yk = oct_bcast<4>(y[0]); break;
+                case 5: yk = oct_bcast<5>(y[0]); break;
+                case 6: yk = oct_bcast<6>(y[0]); break;
+                default: yk = oct_bcast<7>(y[0]); break;
+                }
 #pragma unroll
-                    for (int u = 0; u < 16; ++u)
-                        lnxt[kq][u] = Li[(4 * (ku + 1) + kq) * L + q * 16 + (ku + 1) + u];
+                for (int u = 0; u < 8; ++u) y[u] -= lv[kq][u] * yk;
             }
+            Sg[8 * ku + g][w8] = y[0];
 #pragma unroll
-            for (int kq = 0; kq < 4; ++kq) {
-                const CT yk = kq == 0 ? quad_bcast<0>(y[0]) : kq == 1 ? quad_bcast<1>(y[0])
-                            : kq == 2 ? quad_bcast<2>(y[0]) : quad_bcast<3>(y[0]);
-#pragma unroll
-                for (int u = 0; u < 16; ++u) y[u] -= lcur[kq][u] * yk;
-            }
-#pragma unroll
-            for (int kq = 0; kq < 4; ++kq)
-#pragma unroll
-                for (int u = 0; u < 16; ++u) lcur[kq][u] = lnxt[kq][u];
-            Sg[4 * ku + q][w4] = y[0];
-#pragma unroll
-            for (int u = 0; u < 15; ++u) y[u] = y[u + 1];
-            y[15] = 0;
+            for (int u = 0; u < 7; ++u) y[u] = y[u + 1];
+            y[7] = 0;
         }
         __syncthreads();
-        for (int e = t; e < L * L / CH; e += 256) {
+        for (int e = t; e < L * L / CH; e += NT) {
             const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
             Chunk ch;
 #pragma unroll
@@ -800,8 +829,8 @@ static hipError_t leaf_spec_t(int64_t Np, int64_t c0, void *A, int64_t lda, void
     const int nrt = (int)(below / NB_LEAF);
     const int nct = nrt;
     const unsigned grid = (unsigned)std::max(1, nrt + nct);
-    hipLaunchKernelGGL(k_leaf_spec<T>, dim3(grid), dim3(256), 0, s, Np, c0, (T *)A, lda, (T *)LT,
-                       k0, nrt, nct, (T *)DG, (const T *)DGprev, cprev, flags);
+    hipLaunchKernelGGL(k_leaf_spec<T>, dim3(grid), dim3(LEAF_THREADS), 0, s, Np, c0, (T *)A, lda,
+                       (T *)LT, k0, nrt, nct, (T *)DG, (const T *)DGprev, cprev, flags);
     return hipGetLastError();
 }
 
