@@ -174,6 +174,8 @@ N3P_API size_t n3p_workspace_size(int64_t n, int lu_prec, int linsolver, const n
  *   evaluate F(x) (FP64); tau = tau_r ||F|| + tau_a
  *   while ||F|| > tau:
  *     J = F'(x) stored FP32; J_h = I_s^h(J) in lu_prec (column-scaled for FP16)
+ *     (lu_prec FP64 with a built-in problem factors the FP64 Jacobian itself,
+ *     i.e. plain double-precision Newton; with callbacks it factors J)
  *     factor J_h (partial pivoting); find s with ||J s + F|| <= eta ||F||
  *     by `linsolver` on the unit right-hand side -F/||F|| (eqs. (2.17)-(2.18));
  *     x += s (FP64); evaluate F(x)

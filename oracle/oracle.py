@@ -262,11 +262,15 @@ def heq_mean_closed_form(c: float) -> float:
 # Three-precision method, emulated with numpy dtypes
 # --------------------------------------------------------------------------
 
-_HALF = {"fp16": np.float16}
+_HALF = {"fp16": np.float16, "fp32": np.float32}
 
 
 def round_half(A: np.ndarray, prec: str = "fp16") -> np.ndarray:
-    """I_s^h: round an FP32 array to half precision (IEEE binary16, RNE)."""
+    """I_s^h: round an FP32 array to the factorisation precision (RNE).
+
+    "fp16" is IEEE binary16; "fp32" leaves the FP32 Jacobian as it is (the
+    two-precision method of Section 3.1 factors the single-precision matrix).
+    """
     return np.asarray(A, dtype=np.float32).astype(_HALF[prec])
 
 
@@ -468,6 +472,10 @@ def newton3p(resid: Callable[[np.ndarray], np.ndarray], jac: Callable[[np.ndarra
     half precision; the step equation is scaled to unit norm before it is
     handed to the linear solver (eqs. (2.17)-(2.18)): solve J u = -F/||F|| to
     relative residual ``eta`` by IR or GMRES-IR, then s = ||F|| u in FP64.
+
+    ``solver="direct"`` is the two-precision method of Section 3.1 (the
+    F32 and F16 columns of Tables 2 and 3): the step is one solve with the
+    stored low-precision factors, promoted to FP32, with no refinement.
     """
     x = np.array(x0, dtype=np.float64, copy=True)
     F = resid(x)
@@ -482,6 +490,9 @@ def newton3p(resid: Callable[[np.ndarray], np.ndarray], jac: Callable[[np.ndarra
         b = (-F / fn).astype(np.float32)
         if solver == "ir":
             res = ir(J32, b, lu, max_sweeps=max_sweeps, tol=eta)
+        elif solver == "direct":
+            u = lu.solve(b, np.float32)
+            res = IRResult(u=u, sweeps=1, failed=False, rel_res=0.0)
         elif solver == "gmres":
             res = gmres_ir(J32, b, lu, max_outer=max_sweeps, tol=eta, m=gmres_m,
                            gmres_tol=gmres_tol)

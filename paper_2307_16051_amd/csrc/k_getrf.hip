@@ -51,6 +51,15 @@ template <int K> __device__ __forceinline__ double oct_bcast(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// recip: 1/v.  FP32: hardware reciprocal estimate refined by one Newton-Raphson
+// step (r + r(1 - v r)), within an ulp of the rounded quotient; FP64: division.
+__device__ __forceinline__ float recip(float v)
+{
+    const float r = __builtin_amdgcn_rcpf(v);
+    return fmaf(fmaf(-v, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+
 // =========================================================== leaf (no-swap)
 // Blocks b < nrt: 64 rows of L21 below the leaf; nrt <= b < nrt + nct: 64
 // columns of the U row block to the right of the leaf (when the leaf is the
@@ -88,8 +97,6 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t 
     __shared__ __attribute__((aligned(16))) CT Ui[L * L + 8];
     __shared__ __attribute__((aligned(16))) CT Li[L * L + 8];
     __shared__ __attribute__((aligned(16))) CT Sg[L][LP];       // staging of one tile
-    __shared__ __attribute__((aligned(16))) CT rowbuf[2][4][16];  // pivot row, by lane
-    __shared__ CT pivbuf[2];                                      // pivot value
     __shared__ CT rdiag[L];
     __shared__ int sfail;
     if (block_flag(&flags[FLAG_FAIL])) return;
@@ -114,53 +121,48 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t 
     __syncthreads();
     const CT margin = (CT)(1.0 - 1.0 / 256.0);
     // ---- diagonal block, no interchange, with the partial-pivoting check.
-    // Threads 0..255: quad r (lanes q = 0..3) owns row r; lane q holds
-    // columns 4(kc + c) + q of the current group kc in x[c].  At step k the
-    // quad of row k publishes the row (finished entries as 0) and its pivot;
-    // after one barrier every row below computes its multiplier in the lane
-    // owning column k (lane k % 4, slot 0), checks it, broadcasts it to its
-    // quad and updates its 16 columns.
+    // Blocked by 8-column strips: wave w keeps columns 8w .. 8w+7 of all 64
+    // rows in registers (lane = row).  For panel p, wave p factors its strip
+    // (pivot row entries by readlane, no barrier inside the panel) and stores
+    // it; after one barrier every later wave applies the panel to its own
+    // strip: row k of the strip is final when step k starts, so it is read
+    // by readlane and the multipliers of the panel come from LDS.
     {
-        const bool act = t < 4 * L;
-        const int r = t / 4, q = t % 4;
-        CT x[16];
+        const int w = t / 64, r = t % 64;
+        CT x[8];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) x[c] = act ? Dm[r][4 * c + q] : (CT)0;
+        for (int c = 0; c < 8; ++c) x[c] = Dm[r][8 * w + c];
         bool fail = false;
-        for (int kc = 0; kc < 16; ++kc) {
+        for (int p = 0; p < 8; ++p) {
+            if (w == p) {
 #pragma unroll
-            for (int kq = 0; kq < 4; ++kq) {
-                const int k = 4 * kc + kq, bsel = kq & 1;
-                if (act && r == k) {
-#pragma unroll
-                    for (int c = 0; c < 16; ++c)
-                        rowbuf[bsel][q][c] = (c == 0 && q <= kq) ? (CT)0 : x[c];
-                    if (q == kq) {
-                        pivbuf[bsel] = x[0];
-                        if (!(fabs(x[0]) > (CT)0)) fail = true;
-                    }
-                }
-                __syncthreads();
-                const CT piv = pivbuf[bsel];
-                CT l = 0;
-                if (act && q == kq && r > k) {
+                for (int kk = 0; kk < 8; ++kk) {
+                    const int k = 8 * p + kk;
+                    const CT piv = lane_bcast(x[kk], k);
                     if (!(fabs(piv) > (CT)0)) fail = true;
-                    if (!(fabs(x[0]) <= margin * fabs(piv))) fail = true;
-                    x[0] = x[0] / piv;
-                    l = x[0];
-                }
-                l = kq == 0 ? quad_bcast<0>(l) : kq == 1 ? quad_bcast<1>(l)
-                  : kq == 2 ? quad_bcast<2>(l) : quad_bcast<3>(l);
-                if (act && r > k) {
-                    const CT *pr = &rowbuf[bsel][q][0];
+                    const CT rp = recip(piv);
+                    CT l = 0;
+                    if (r > k) {
+                        if (!(fabs(x[kk]) <= margin * fabs(piv))) fail = true;
+                        l = x[kk] * rp;
+                        x[kk] = l;
+                    }
 #pragma unroll
-                    for (int c = 0; c < 16; ++c) x[c] -= l * pr[c];
+                    for (int c = kk + 1; c < 8; ++c) x[c] -= l * lane_bcast(x[c], k);
                 }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) Dm[r][8 * p + c] = x[c];
             }
-            if (act) Dm[r][4 * kc + q] = x[0];  // column 4kc+q of row r is final
+            __syncthreads();
+            if (w > p) {
+                CT l[8];
 #pragma unroll
-            for (int c = 0; c < 15; ++c) x[c] = x[c + 1];
-            x[15] = 0;
+                for (int kk = 0; kk < 8; ++kk) l[kk] = r > 8 * p + kk ? Dm[r][8 * p + kk] : (CT)0;
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) x[c] -= l[kk] * lane_bcast(x[c], 8 * p + kk);
+            }
         }
         if (fail) sfail = 1;
     }

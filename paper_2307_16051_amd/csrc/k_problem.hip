@@ -11,6 +11,7 @@
 // scale against the narrow FP16 range (Section 1.2, Table 1).
 #include <algorithm>
 
+#include <type_traits>
 #include "n3p_internal.hpp"
 
 namespace n3p {
@@ -143,8 +144,11 @@ __global__ __launch_bounds__(256) void k_heq_jac_round(int64_t n, int64_t Np, do
         // recompute in the same order so the FP32 value is identical to J's
         const double di = D[i];
         const double kij = wgt * ((double)i + 0.5) * (h ? h[i + j] : 1.0 / (double)(i + j + 1));
-        const float vf = (float)((i == j ? 1.0 : 0.0) - kij / (di * di));
-        col[i] = cvt_out<T>(vf * s);
+        const double v = (i == j ? 1.0 : 0.0) - kij / (di * di);
+        if constexpr (std::is_same<T, double>::value)
+            col[i] = v;  // a double-precision factorisation takes the FP64 Jacobian itself
+        else
+            col[i] = cvt_out<T>((float)v * s);
     }
     for (int64_t i = n + t; i < Np; i += 256) col[i] = cvt_out<T>(0.0f);
 }
@@ -223,6 +227,31 @@ __global__ __launch_bounds__(256) void k_dense_tanh_jac(int64_t n, const double 
         if (i == j) v += 0.1 * (1.0 - tj * tj);
         J[i + j * ldj] = (float)v;
     }
+}
+
+// The same Jacobian for a double-precision factorisation: FP32 copy J (used
+// by the refinement residual) plus the unrounded FP64 values in the padded
+// Np x Np factor buffer Ah (identity padding).  One block per column of Ah.
+__global__ __launch_bounds__(256) void k_dense_tanh_jac_f64(int64_t n, int64_t Np,
+                                                            const double *__restrict__ A,
+                                                            int64_t lda, const double *__restrict__ x,
+                                                            float *__restrict__ J, int64_t ldj,
+                                                            double *__restrict__ Ah, int64_t ldh)
+{
+    const int64_t j = blockIdx.x;
+    double *col = Ah + j * ldh;
+    if (j >= n) {
+        for (int64_t i = threadIdx.x; i < Np; i += 256) col[i] = i == j ? 1.0 : 0.0;
+        return;
+    }
+    const double tj = tanh(x[j]);
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        double v = A[i + j * lda];
+        if (i == j) v += 0.1 * (1.0 - tj * tj);
+        J[i + j * ldj] = (float)v;
+        col[i] = v;
+    }
+    for (int64_t i = n + threadIdx.x; i < Np; i += 256) col[i] = 0.0;
 }
 
 // ----------------------------------------------------------- reductions
@@ -429,6 +458,15 @@ hipError_t launch_dense_tanh_jacobian(int64_t n, const double *A, int64_t lda, c
                                       float *J, int64_t ldj, hipStream_t s)
 {
     hipLaunchKernelGGL(k_dense_tanh_jac, dim3((unsigned)n), dim3(256), 0, s, n, A, lda, x, J, ldj);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_tanh_jacobian_f64(int64_t n, int64_t Np, const double *A, int64_t lda,
+                                          const double *x, float *J, int64_t ldj, double *Ah,
+                                          int64_t ldh, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dense_tanh_jac_f64, dim3((unsigned)Np), dim3(256), 0, s, n, Np, A, lda, x,
+                       J, ldj, Ah, ldh);
     return hipGetLastError();
 }
 

@@ -592,7 +592,14 @@ static int build_jacobian(const n3p_problem *p, const SolveWs &w, const double *
         HIPCHK(launch_heq_jac_round(w.prec, w.n, w.Np, p->c, w.D, w.h, w.J, w.n, w.f.A, w.Np, cs,
                                     tl, w.f.flags, s));
         return 0;
-    case 1: HIPCHK(launch_dense_tanh_jacobian(w.n, p->A, p->lda, x, w.J, w.n, s)); break;
+    case 1:
+        if (w.prec == N3P_FP64) {  // the FP64 factorisation takes the unrounded Jacobian
+            HIPCHK(launch_dense_tanh_jacobian_f64(w.n, w.Np, p->A, p->lda, x, w.J, w.n,
+                                                  (double *)w.f.A, w.Np, s));
+            return 0;
+        }
+        HIPCHK(launch_dense_tanh_jacobian(w.n, p->A, p->lda, x, w.J, w.n, s));
+        break;
     case 2:
         if (p->jacobian(p->ctx, x, w.J, w.n, w.n, (void *)s) != 0) return N3P_E_CALLBACK;
         break;
@@ -708,6 +715,9 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
             CHK(tstop(&t_jac));
             CHK(tstart());
             auto refill = [&]() -> int {
+                // the FP64 factorisation of a built-in problem takes the FP64
+                // Jacobian again (J holds only its FP32 rounding)
+                if (w.prec == N3P_FP64 && p->kind != 2) return build_jacobian(p, w, x, tl, scaled, s);
                 HIPCHK(launch_round_scale(w.prec, n, w.Np, w.J, n, w.f.A, w.Np,
                                           scaled ? w.colscale : nullptr, tl, w.f.flags, s));
                 return 0;

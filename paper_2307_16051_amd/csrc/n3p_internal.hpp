@@ -126,6 +126,9 @@ hipError_t launch_dense_tanh_residual(int64_t n, const double *A, int64_t lda, c
                                       const double *x, double *F, double *part, hipStream_t s);
 hipError_t launch_dense_tanh_jacobian(int64_t n, const double *A, int64_t lda, const double *x,
                                       float *J, int64_t ldj, hipStream_t s);
+hipError_t launch_dense_tanh_jacobian_f64(int64_t n, int64_t Np, const double *A, int64_t lda,
+                                          const double *x, float *J, int64_t ldj, double *Ah,
+                                          int64_t ldh, hipStream_t s);
 // J (FP32, n x n) -> padded Np x Np copy in prec, column scales (may be null)
 hipError_t launch_round_scale(int prec, int64_t n, int64_t Np, const float *J, int64_t ldj,
                               void *Ah, int64_t ldh, float *colscale, float target_log2,

@@ -87,6 +87,27 @@ def test_table3_gmres_ir_tracks_f64(table3):
     assert abs(r.rel_hist[8] / expect[8] - 1.0) < 0.02
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("tab,c,k", [("table2", 0.99, 5), ("table3", 0.9999, 8)])
+def test_two_precision_f32_column(request, tab, c, k):
+    """Tables 2 and 3, F32 column: the FP32 Jacobian factored in FP32, one solve per step.
+
+    Entries before the last agree to every printed digit; the last depends on
+    rounding inside the factorisation and agrees within 2%.  (The F16 column
+    comes from a factorisation that rounds every operation to half precision,
+    which the emulation here does not reproduce: that column is not pinned.)
+    """
+    table = request.getfixturevalue(tab)
+    n = 4096
+    R = lambda x: O.heq_residual(x, c)
+    Jf = lambda x: O.heq_jacobian(x, c)
+    r = O.newton3p(R, Jf, np.ones(n), tau_r=1e-9, solver="direct", prec="fp32")
+    expect = [v for v in table["F32"] if v is not None]
+    assert r.its == len(expect) - 1 == k
+    assert [printed(v) for v in r.rel_hist[:k]] == expect[:k]
+    assert abs(r.rel_hist[k] / expect[k] - 1.0) < 0.02
+
+
 # ------------------------------------------------------------ closed forms
 
 @pytest.mark.parametrize("c", [0.5, 0.9, 0.99, 0.9999])
