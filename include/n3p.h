@@ -53,7 +53,10 @@ typedef enum n3p_status {
     N3P_E_NONFINITE = -4,   /* Inf/NaN in F, J or the factors after the scaling retry */
     N3P_E_CALLBACK = -5,    /* a user callback returned non-zero */
     N3P_E_HIP = -6,         /* a HIP runtime call failed */
-    N3P_E_TIMEOUT = -7      /* a device-side bounded wait expired (never expected) */
+    N3P_E_TIMEOUT = -7,     /* a device-side bounded wait expired (never expected) */
+    N3P_E_PIVOTING = -8     /* batched engine only: the matrix needs row interchanges
+                               (partial pivoting would not keep the diagonal); solve it
+                               with n3p_solve, which pivots */
 } n3p_status;
 
 /* Human-readable name of a status code (static storage). */
@@ -264,6 +267,79 @@ N3P_API int n3p_gmres_ir(int prec, int64_t n, const float *A, int64_t lda, const
 /* Workspace bytes for n3p_ir / n3p_gmres_ir / n3p_gemv_resid_f32 at size n
  * with Krylov dimension m (ignored for IR). */
 N3P_API size_t n3p_linsolve_workspace_size(int64_t n, int m);
+
+/* ===================================================== batched engine (serving)
+ * Many independent H-equation solves (eq. (3.2), x0 = ones) advance through
+ * Algorithm 2.1 together: one engine step is one Newton iteration for every
+ * admitted request (Jacobian stored FP32 and rounded to lu_prec, the
+ * no-interchange half-precision LU verified against partial pivoting, IR
+ * sweeps of Algorithm 2.2 with the Section 3.1 policy, FP64 update and
+ * residual), as batched kernels over a device table of slots, replayed from
+ * captured HIP graphs.  Requests join between steps as slots and pool memory
+ * free up and leave when their stopping test passes.  A request's arithmetic
+ * does not depend on the other requests present: results are identical alone
+ * and in any mix.  Limits: N <= 4096, lu_prec FP16 or BF16, linear solver IR;
+ * a matrix that needs row interchanges ends with N3P_E_PIVOTING (use
+ * n3p_solve).  All device memory comes from the caller's pool; the engine
+ * runs on a stream of its own (default priority) that waits for `stream` at
+ * creation, and every call returns after that stream has drained. */
+typedef struct n3p_engine n3p_engine; /* opaque host object */
+
+typedef struct n3p_engine_config {
+    int max_slots;   /* requests in flight at once, 1..256 */
+    int64_t max_n;   /* largest admitted N, padded size <= 4096 */
+    int lu_prec;     /* N3P_FP16 or N3P_BF16 */
+    int use_graphs;  /* 1: capture the step phases once and replay them */
+    int leaf_grid;   /* persistent grid of the leaf kernel (workgroups) */
+    int gemm_grid;   /* persistent grid of the rank-64 update */
+    int gemm_kc;     /* K chunk of the update tile (32 or 64) */
+    int vec_grid;    /* grid of the residual, Jacobian and matvec kernels */
+} n3p_engine_config;
+
+typedef struct n3p_serve_stats {
+    double p50_ms, p99_ms, mean_ms, max_ms; /* arrival to result, per request */
+    double makespan_s, solves_per_s;        /* wall time of the whole stream */
+    int max_active, steps;                  /* most requests in flight; engine steps */
+} n3p_serve_stats;
+
+N3P_API void n3p_engine_default_config(n3p_engine_config *cfg);
+/* Pool bytes one request of size n holds while admitted (0 if not allowed). */
+N3P_API size_t n3p_engine_request_bytes(int64_t n, int lu_prec);
+/* Pool bytes the engine itself keeps for max_slots slots (the slot table). */
+N3P_API size_t n3p_engine_fixed_bytes(int max_slots);
+/* pool: caller-owned device memory, kept until destroy; opt may be NULL. */
+N3P_API int n3p_engine_create(n3p_engine **e, const n3p_engine_config *cfg,
+                              const n3p_options *opt, void *pool, size_t pool_bytes,
+                              void *stream);
+N3P_API int n3p_engine_destroy(n3p_engine *e);
+/* Admit H-equation (n, c); returns the slot.  N3P_E_NOMEM: no slot or pool
+ * space free right now (try again after a step frees one). */
+N3P_API int n3p_engine_admit(n3p_engine *e, int64_t n, double c, int *slot);
+/* One Newton iteration for every admitted request; n_done = requests whose
+ * result is ready to collect. */
+N3P_API int n3p_engine_step(n3p_engine *e, int *n_done);
+/* phase: 0 free, 1 admitted, 2 iterating, 3 done; its: Newton steps so far. */
+N3P_API int n3p_engine_slot_state(const n3p_engine *e, int slot, int *phase, int *its);
+/* Copy a finished request's x (FP64, n entries) to device x_out (may be NULL),
+ * fill rep (may be NULL) and free the slot. */
+N3P_API int n3p_engine_collect(n3p_engine *e, int slot, double *x_out, n3p_report *rep);
+N3P_API int n3p_engine_largest_free(const n3p_engine *e, size_t *bytes);
+/* Time the factorisation phase of the admitted (not yet stepped) requests for
+ * each candidate (leaf grid, update grid, update K chunk), keep the fastest
+ * in the engine and return it; ms_out (may be NULL) gets one time per
+ * candidate (24 candidates). */
+N3P_API int n3p_engine_autotune(n3p_engine *e, n3p_engine_config *chosen, float *ms_out,
+                                int *n_candidates);
+/* Continuous batching over `count` requests (n[i], c[i]) arriving at
+ * arrival_s[i] seconds (non-decreasing) after the call starts: admitted in
+ * order as slots and pool memory allow, stepped together, results copied to
+ * x_out + x_off[i] (device FP64; x_out may be NULL).  its/status/latency_ms
+ * (host, may be NULL) per request; stats (may be NULL) for the stream.
+ * N3P_E_NOMEM if a request can never fit the pool. */
+N3P_API int n3p_serve(const n3p_engine_config *cfg, const n3p_options *opt, void *pool,
+                      size_t pool_bytes, int count, const int64_t *n, const double *c,
+                      const double *arrival_s, double *x_out, const int64_t *x_off, int *its,
+                      int *status, double *latency_ms, n3p_serve_stats *stats, void *stream);
 
 #ifdef __cplusplus
 }

@@ -15,4 +15,6 @@ from ._binding import (  # noqa: F401
     Options, Report, N3PError, lib, lib_path, status_str, version,
     workspace_size, solve_heq, solve_dense_tanh, solve,
     getrf, getrs, gemv_resid, heq_residual, heq_jacobian, ir, gmres_ir,
+    EngineConfig, ServeStats, Engine, serve, engine_request_bytes, engine_fixed_bytes,
+    PHASE_FREE, PHASE_ADMITTED, PHASE_RUNNING, PHASE_DONE,
 )

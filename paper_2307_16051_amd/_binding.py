@@ -313,3 +313,159 @@ def gmres_ir(A: torch.Tensor, LU: torch.Tensor, ipiv, b: torch.Tensor, u: torch.
                             ctypes.byref(fl), ctypes.byref(rr), _ptr(ws), ws.numel(), _stream()),
            "n3p_gmres_ir")
     return sw.value, gi.value, bool(fl.value), rr.value
+
+
+# ----------------------------------------------------------- batched engine
+class EngineConfig(ctypes.Structure):
+    _fields_ = [("max_slots", _int), ("max_n", _i64), ("lu_prec", _int), ("use_graphs", _int),
+                ("leaf_grid", _int), ("gemm_grid", _int), ("gemm_kc", _int), ("vec_grid", _int)]
+
+    @classmethod
+    def default(cls, **kw) -> "EngineConfig":
+        c = cls()
+        lib.n3p_engine_default_config(ctypes.byref(c))
+        for k, v in kw.items():
+            if not hasattr(c, k):
+                raise AttributeError(k)
+            setattr(c, k, v)
+        return c
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("p50_ms", _f64), ("p99_ms", _f64), ("mean_ms", _f64), ("max_ms", _f64),
+                ("makespan_s", _f64), ("solves_per_s", _f64), ("max_active", _int),
+                ("steps", _int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _setup_engine():
+    L = lib
+    L.n3p_engine_default_config.argtypes = [ctypes.POINTER(EngineConfig)]
+    L.n3p_engine_default_config.restype = None
+    L.n3p_engine_request_bytes.argtypes = [_i64, _int]
+    L.n3p_engine_request_bytes.restype = ctypes.c_size_t
+    L.n3p_engine_fixed_bytes.argtypes = [_int]
+    L.n3p_engine_fixed_bytes.restype = ctypes.c_size_t
+    L.n3p_engine_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(EngineConfig),
+                                    ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp]
+    L.n3p_engine_destroy.argtypes = [_vp]
+    L.n3p_engine_admit.argtypes = [_vp, _i64, _f64, _ip]
+    L.n3p_engine_step.argtypes = [_vp, _ip]
+    L.n3p_engine_slot_state.argtypes = [_vp, _int, _ip, _ip]
+    L.n3p_engine_collect.argtypes = [_vp, _int, _vp, ctypes.POINTER(_Report)]
+    L.n3p_engine_largest_free.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.n3p_engine_autotune.argtypes = [_vp, ctypes.POINTER(EngineConfig),
+                                      ctypes.POINTER(ctypes.c_float), _ip]
+    L.n3p_serve.argtypes = [ctypes.POINTER(EngineConfig), ctypes.POINTER(Options), _vp,
+                            ctypes.c_size_t, _int, ctypes.POINTER(_i64), _dp, _dp, _vp,
+                            ctypes.POINTER(_i64), _ip, _ip, _dp, ctypes.POINTER(ServeStats), _vp]
+    for name in ("n3p_engine_create", "n3p_engine_destroy", "n3p_engine_admit", "n3p_engine_step",
+                 "n3p_engine_slot_state", "n3p_engine_collect", "n3p_engine_largest_free",
+                 "n3p_engine_autotune", "n3p_serve"):
+        getattr(L, name).restype = _int
+
+
+_setup_engine()
+
+PHASE_FREE, PHASE_ADMITTED, PHASE_RUNNING, PHASE_DONE = 0, 1, 2, 3
+
+
+def engine_request_bytes(n: int, prec: int = FP16) -> int:
+    return int(lib.n3p_engine_request_bytes(n, prec))
+
+
+def engine_fixed_bytes(max_slots: int) -> int:
+    return int(lib.n3p_engine_fixed_bytes(max_slots))
+
+
+class Engine:
+    """n3p_engine: batched H-equation solves sharing one device pool (a torch tensor)."""
+
+    def __init__(self, pool: torch.Tensor, cfg: Optional[EngineConfig] = None,
+                 opts: Optional[Options] = None):
+        self.cfg = cfg or EngineConfig.default()
+        self.opts = opts or Options.default()
+        self.pool = pool
+        h = _vp()
+        _check(lib.n3p_engine_create(ctypes.byref(h), ctypes.byref(self.cfg), ctypes.byref(self.opts),
+                                     _ptr(pool), pool.numel() * pool.element_size(), _stream()),
+               "n3p_engine_create")
+        self._h = h
+
+    def admit(self, n: int, c: float) -> Optional[int]:
+        """Slot index, or None if no slot / pool space is free right now."""
+        slot = _int(-1)
+        st = lib.n3p_engine_admit(self._h, n, c, ctypes.byref(slot))
+        if st == -2:
+            return None
+        _check(st, "n3p_engine_admit")
+        return slot.value
+
+    def step(self) -> int:
+        nd = _int(0)
+        _check(lib.n3p_engine_step(self._h, ctypes.byref(nd)), "n3p_engine_step")
+        return nd.value
+
+    def state(self, slot: int):
+        ph, its = _int(0), _int(0)
+        _check(lib.n3p_engine_slot_state(self._h, slot, ctypes.byref(ph), ctypes.byref(its)),
+               "n3p_engine_slot_state")
+        return ph.value, its.value
+
+    def collect(self, slot: int, x_out: Optional[torch.Tensor]) -> Report:
+        rep = _Report()
+        _check(lib.n3p_engine_collect(self._h, slot, _ptr(x_out), ctypes.byref(rep)),
+               "n3p_engine_collect")
+        return Report.from_c(rep)
+
+    def largest_free(self) -> int:
+        v = ctypes.c_size_t(0)
+        _check(lib.n3p_engine_largest_free(self._h, ctypes.byref(v)), "n3p_engine_largest_free")
+        return v.value
+
+    def autotune(self):
+        best = EngineConfig()
+        ms = (ctypes.c_float * 64)()
+        nc = _int(0)
+        _check(lib.n3p_engine_autotune(self._h, ctypes.byref(best), ms, ctypes.byref(nc)),
+               "n3p_engine_autotune")
+        self.cfg = best
+        return best, list(ms[: nc.value])
+
+    def close(self):
+        if self._h:
+            lib.n3p_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve(ns, cs, arrivals, pool: torch.Tensor, cfg: Optional[EngineConfig] = None,
+          opts: Optional[Options] = None, x_out: Optional[torch.Tensor] = None, x_off=None):
+    """n3p_serve: continuous batching of H-equation requests; returns (its, status,
+    latency_ms, stats dict).  x_out (FP64 device) receives each result at x_off[i]."""
+    cfg = cfg or EngineConfig.default()
+    opts = opts or Options.default()
+    k = len(ns)
+    n_a = (_i64 * k)(*[int(v) for v in ns])
+    c_a = (_f64 * k)(*[float(v) for v in cs])
+    t_a = (_f64 * k)(*[float(v) for v in arrivals])
+    off_a = (_i64 * k)(*[int(v) for v in x_off]) if x_off is not None else None
+    its = (_int * k)()
+    status = (_int * k)()
+    lat = (_f64 * k)()
+    stats = ServeStats()
+    st = lib.n3p_serve(ctypes.byref(cfg), ctypes.byref(opts), _ptr(pool),
+                       pool.numel() * pool.element_size(), k, n_a, c_a, t_a, _ptr(x_out), off_a,
+                       its, status, lat, ctypes.byref(stats), _stream())
+    _check(st, "n3p_serve")
+    return list(its), list(status), list(lat), stats.as_dict()

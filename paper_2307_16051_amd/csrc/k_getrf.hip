@@ -61,30 +61,33 @@ __device__ __forceinline__ float recip(float v)
 __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
 
 // =========================================================== leaf (no-swap)
-// Blocks b < nrt: 64 rows of L21 below the leaf; nrt <= b < nrt + nct: 64
+// Tile b < nrt: 64 rows of L21 below the leaf; nrt <= b < nrt + nct: 64
 // columns of the U row block to the right of the leaf (when the leaf is the
-// last one, a single block only stores the diagonal block).  Every block first
-// factors the 64x64 diagonal block itself (identical arithmetic in every
-// block), so no block waits for another.  The factored diagonal block goes to
-// DG (a side buffer): blocks still reading the unfactored block from A must
-// not see it change.  DGprev (if non-null) is the previous leaf's diagonal
-// block, copied into A by block 0 (nothing else touches that region now).
+// last one, a single tile only stores the diagonal block).  Every workgroup
+// first factors the 64x64 diagonal block itself (identical arithmetic in
+// every workgroup), so none waits for another.  The factored diagonal block
+// goes to DG (a side buffer): workgroups still reading the unfactored block
+// from A must not see it change; with DG null (allowed only when the leaf has
+// no tiles) it goes straight to A.  DGprev (if non-null) is the previous
+// leaf's diagonal block, copied into A by tile 0 (nothing else touches that
+// region now).  L21 is also written transposed to LT (row i at
+// LT + i * ldlt + ltcol, K contiguous) for the Schur update.
 //
-// Every column step is a short dependent chain, so the work is spread over
-// lanes and kept on the VALU path: the diagonal LU uses four lanes per row
-// (pivot row through LDS, multipliers by DPP quad broadcast, one barrier per
-// step); the triangular solves use eight lanes per row or column (DPP8
-// broadcasts, no barrier).  Column loops run in groups whose index is a
-// runtime loop while the steps inside are unrolled; per-lane register arrays
-// rotate after each group so every register index stays static.
+// Every column step is a short dependent chain, so the work stays on the
+// VALU path: the diagonal LU is blocked by 8-column strips held one row per
+// lane (readlane broadcasts, one barrier per strip); the triangular solves
+// use eight lanes per row or column (DPP broadcasts, no barrier).  Column
+// loops run in groups whose index is a runtime loop while the steps inside
+// are unrolled; per-lane register arrays rotate after each group so every
+// register index stays static.
 constexpr int LEAF_THREADS = 512;
 
 template <typename T>
-__global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t c0, T *__restrict__ A,
-                                                            int64_t lda, T *__restrict__ LT, int64_t k0,
-                                                            int nrt, int nct, T *__restrict__ DG,
-                                                            const T *__restrict__ DGprev, int64_t cprev,
-                                                            int *__restrict__ flags)
+__device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__restrict__ A,
+                                          int64_t lda, T *__restrict__ LT, int64_t ldlt,
+                                          int64_t ltcol, int nrt, int nct, T *__restrict__ DG,
+                                          const T *__restrict__ DGprev, int64_t cprev,
+                                          int *__restrict__ flags)
 {
     typedef typename compute_of<T>::type CT;
     constexpr int L = NB_LEAF;
@@ -101,7 +104,6 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t 
     __shared__ int sfail;
     if (block_flag(&flags[FLAG_FAIL])) return;
     const int t = threadIdx.x;
-    const int bid = blockIdx.x;
     if (bid == 0 && DGprev) {
         for (int e = t; e < L * L; e += NT) {
             const int i = e % L, j = e / L;
@@ -182,7 +184,9 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t 
     if (bid == 0) {
         for (int e = t; e < L * L; e += NT) {
             const int i = e % L, j = e / L;
-            DG[i + j * L] = to_store_d<T>((double)Dm[i][j]);
+            const T v = to_store_d<T>((double)Dm[i][j]);
+            if (DG) DG[i + j * L] = v;
+            else A[(c0 + i) + (c0 + j) * lda] = v;
         }
     }
     __syncthreads();
@@ -256,7 +260,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t 
             Chunk ch;
 #pragma unroll
             for (int u = 0; u < CH; ++u) ch.e[u] = to_store_d<T>((double)Sg[i][j0 + u]);
-            *(uint4 *)(LT + (R0 + i) * (int64_t)NB_OUT + (c0 - k0) + j0) = ch.v;
+            *(uint4 *)(LT + (R0 + i) * ldlt + ltcol + j0) = ch.v;
         }
         if (fail) set_flag(&flags[FLAG_FAIL], 1);
     } else if (bid - nrt < nct) {
@@ -317,6 +321,16 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t 
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
 }
 
+template <typename T>
+__global__ __launch_bounds__(LEAF_THREADS) void k_leaf_spec(int64_t Np, int64_t c0, T *__restrict__ A,
+                                                            int64_t lda, T *__restrict__ LT, int64_t k0,
+                                                            int nrt, int nct, T *__restrict__ DG,
+                                                            const T *__restrict__ DGprev, int64_t cprev,
+                                                            int *__restrict__ flags)
+{
+    leaf_body<T>(blockIdx.x, Np, c0, A, lda, LT, NB_OUT, c0 - k0, nrt, nct, DG, DGprev, cprev, flags);
+}
+
 // copy a 64x64 diagonal block from DG into A (the last leaf's block)
 template <typename T>
 __global__ __launch_bounds__(256) void k_put_diag(int64_t c0, T *__restrict__ A, int64_t lda,
@@ -351,11 +365,9 @@ template <> struct mfma32<bf16> {
 };
 
 template <typename T, int TM, int TN, int WGM, int WGN, int KC>
-__global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
-                                                          const T *__restrict__ At, int64_t ldat,
-                                                          const T *__restrict__ B, int64_t ldb,
-                                                          T *__restrict__ C, int64_t ldc,
-                                                          int *__restrict__ flags, int check_abort)
+__device__ __forceinline__ void gemm16_tile(int row0, int col0, int K, const T *__restrict__ At,
+                                            int64_t ldat, const T *__restrict__ B, int64_t ldb,
+                                            T *__restrict__ C, int64_t ldc, int *__restrict__ flags)
 {
     typedef typename mfma32<T>::vec vec;
     constexpr int NT = WGM * WGN * 64;
@@ -368,15 +380,6 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
     __shared__ __attribute__((aligned(16))) T As[2][TM * KP];
     __shared__ __attribute__((aligned(16))) T Bs[2][TN * KP];
 
-    if (check_abort && block_flag(&flags[FLAG_FAIL])) return;
-    const int ntm = M / TM, ntn = N / TN, nt = ntm * ntn;
-    const int bid = blockIdx.x;
-    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs;
-    // give each XCD a contiguous run of tiles (shared B columns stay in its L2)
-    int tile = bid;
-    if ((nt & 7) == 0) tile = (bid & 7) * (nt >> 3) + (bid >> 3);
-    const int tm = tile % ntm, tn = tile / ntm;
-    const int row0 = tm * TM, col0 = tn * TN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
 
@@ -466,6 +469,24 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
             }
         }
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
+}
+
+template <typename T, int TM, int TN, int WGM, int WGN, int KC>
+__global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
+                                                          const T *__restrict__ At, int64_t ldat,
+                                                          const T *__restrict__ B, int64_t ldb,
+                                                          T *__restrict__ C, int64_t ldc,
+                                                          int *__restrict__ flags, int check_abort)
+{
+    if (check_abort && block_flag(&flags[FLAG_FAIL])) return;
+    const int ntm = M / TM, ntn = N / TN, nt = ntm * ntn;
+    const int bid = blockIdx.x;
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs;
+    // give each XCD a contiguous run of tiles (shared B columns stay in its L2)
+    int tile = bid;
+    if ((nt & 7) == 0) tile = (bid & 7) * (nt >> 3) + (bid >> 3);
+    const int tm = tile % ntm, tn = tile / ntm;
+    gemm16_tile<T, TM, TN, WGM, WGN, KC>(tm * TM, tn * TN, K, At, ldat, B, ldb, C, ldc, flags);
 }
 
 // ========================================== Schur GEMM, FP32/FP64 matrix cores
@@ -991,6 +1012,93 @@ hipError_t launch_check_factor_finite(int prec, int64_t Np, const void *A, int64
     case N3P_FP32: hipLaunchKernelGGL(k_check_finite<float>, dim3((unsigned)Np), dim3(256), 0, s, Np, (const float *)A, lda, flags); break;
     case N3P_FP64: hipLaunchKernelGGL(k_check_finite<double>, dim3((unsigned)Np), dim3(256), 0, s, Np, (const double *)A, lda, flags); break;
     default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+
+// ====================================================== batched engine kernels
+// Leaf `leaf` (columns 64 leaf .. +64) of every slot that factors this step:
+// the same leaf body as the single factorisation, with L21 kept transposed in
+// the slot's LT (ld 64) for the rank-64 update that follows.  A slot's last
+// leaf has no tiles and writes its diagonal block straight into A.
+template <typename T>
+__global__ __launch_bounds__(LEAF_THREADS) void k_b_leaf(const BDesc *__restrict__ d,
+                                                         const BState *__restrict__ st, int nslots,
+                                                         int leaf)
+{
+    __shared__ int off[B_MAX_SLOTS + 1];
+    const int64_t c0 = (int64_t)leaf * NB_LEAF;
+    const int total = b_offsets(nslots, off, [&](int s) {
+        if (st[s].phase != BP_RUN || !st[s].factor || d[s].Np <= c0) return 0;
+        const int nrt = (int)((d[s].Np - c0 - NB_LEAF) / NB_LEAF);
+        return nrt > 0 ? 2 * nrt : 1;
+    });
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = b_find(off, nslots, item);
+        const BDesc &q = d[s];
+        const int nrt = (int)((q.Np - c0 - NB_LEAF) / NB_LEAF);
+        T *DGs = (T *)q.DG;
+        T *DG = nrt > 0 ? DGs + (leaf % 2) * NB_LEAF * NB_LEAF : nullptr;
+        const T *DGprev = leaf > 0 ? DGs + ((leaf - 1) % 2) * NB_LEAF * NB_LEAF : nullptr;
+        leaf_body<T>(item - off[s], q.Np, c0, (T *)q.A, q.Np, (T *)q.LT, NB_LEAF, 0, nrt, nrt, DG,
+                     DGprev, c0 - NB_LEAF, q.flags);
+        __syncthreads();
+    }
+}
+
+// Rank-64 Schur update after leaf `leaf`: A22 -= L21 U12 for every slot that
+// factors this step, in TM x TM tiles (TM = 64: every trailing size is a
+// multiple of 64).
+template <typename T, int KC>
+__global__ __launch_bounds__(256) void k_b_gemm(const BDesc *__restrict__ d,
+                                                const BState *__restrict__ st, int nslots, int leaf)
+{
+    constexpr int TM = 64;
+    __shared__ int off[B_MAX_SLOTS + 1];
+    const int64_t c0 = (int64_t)leaf * NB_LEAF, c1 = c0 + NB_LEAF;
+    const int total = b_offsets(nslots, off, [&](int s) {
+        if (st[s].phase != BP_RUN || !st[s].factor || d[s].Np <= c1) return 0;
+        const int m = (int)((d[s].Np - c1) / TM);
+        return m * m;
+    });
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = b_find(off, nslots, item);
+        const BDesc &q = d[s];
+        if (ld_flag(&q.flags[FLAG_FAIL])) continue;  // abandoned: needs interchanges
+        const int m = (int)((q.Np - c1) / TM), local = item - off[s];
+        const int tm = local % m, tn = local / m;
+        T *A = (T *)q.A;
+        const int64_t Np = q.Np;
+        gemm16_tile<T, TM, TM, 2, 2, KC>(tm * TM, tn * TM, NB_LEAF, (const T *)q.LT + c1 * NB_LEAF,
+                                         NB_LEAF, A + c0 + c1 * Np, Np, A + c1 + c1 * Np, Np,
+                                         q.flags);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_b_leaf(int prec, const BDesc *d, const BState *st, int nslots, int leaf,
+                         int grid, hipStream_t s)
+{
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_b_leaf<f16>, dim3(grid), dim3(LEAF_THREADS), 0, s, d, st, nslots, leaf); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_b_leaf<bf16>, dim3(grid), dim3(LEAF_THREADS), 0, s, d, st, nslots, leaf); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_b_gemm(int prec, const BDesc *d, const BState *st, int nslots, int leaf,
+                         int kc, int grid, hipStream_t s)
+{
+    if (prec == N3P_FP16) {
+        if (kc == 64) hipLaunchKernelGGL((k_b_gemm<f16, 64>), dim3(grid), dim3(256), 0, s, d, st, nslots, leaf);
+        else hipLaunchKernelGGL((k_b_gemm<f16, 32>), dim3(grid), dim3(256), 0, s, d, st, nslots, leaf);
+    } else if (prec == N3P_BF16) {
+        if (kc == 64) hipLaunchKernelGGL((k_b_gemm<bf16, 64>), dim3(grid), dim3(256), 0, s, d, st, nslots, leaf);
+        else hipLaunchKernelGGL((k_b_gemm<bf16, 32>), dim3(grid), dim3(256), 0, s, d, st, nslots, leaf);
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

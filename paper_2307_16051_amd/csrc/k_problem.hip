@@ -28,12 +28,12 @@ __global__ void k_hinv(int64_t m, double *h)
 // j = t, t + 256, ... in FP64; the block reduces in a fixed order.
 constexpr int HR = 16;
 
-__global__ __launch_bounds__(256) void k_heq_residual(int64_t n, double c, const double *__restrict__ x,
-                                                      const double *__restrict__ h,
-                                                      double *__restrict__ F, double *__restrict__ D)
+__device__ __forceinline__ void heq_residual_rows(int64_t i0, int64_t n, double c,
+                                                  const double *__restrict__ x,
+                                                  const double *__restrict__ h,
+                                                  double *__restrict__ F, double *__restrict__ D,
+                                                  double (*red)[257])
 {
-    __shared__ double red[HR][257];
-    const int64_t i0 = (int64_t)blockIdx.x * HR;
     const int t = threadIdx.x;
     double acc[HR];
 #pragma unroll
@@ -65,6 +65,14 @@ __global__ __launch_bounds__(256) void k_heq_residual(int64_t n, double c, const
             F[i] = x[i] - 1.0 / d;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_heq_residual(int64_t n, double c, const double *__restrict__ x,
+                                                      const double *__restrict__ h,
+                                                      double *__restrict__ F, double *__restrict__ D)
+{
+    __shared__ double red[HR][257];
+    heq_residual_rows((int64_t)blockIdx.x * HR, n, c, x, h, F, D, red);
 }
 
 // Column-scale exponent: scale 2^e maps the column max m into
@@ -103,16 +111,14 @@ __device__ __forceinline__ float block_max_256(float v, float *sh)
 // matrix.  Writes J (FP32, rows < n) and the factorisation copy Ah (type T,
 // Np rows, identity padding) with column scale colscale[j] (if non-null).
 template <typename T>
-__global__ __launch_bounds__(256) void k_heq_jac_round(int64_t n, int64_t Np, double c,
-                                                       const double *__restrict__ D,
-                                                       const double *__restrict__ h,
-                                                       float *__restrict__ J, int64_t ldj,
-                                                       T *__restrict__ Ah, int64_t ldh,
-                                                       float *__restrict__ colscale,
-                                                       float target_log2, int *flags)
+__device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np, double c,
+                                               const double *__restrict__ D,
+                                               const double *__restrict__ h,
+                                               float *__restrict__ J, int64_t ldj,
+                                               T *__restrict__ Ah, int64_t ldh,
+                                               float *__restrict__ colscale, float target_log2,
+                                               int *flags, float *sh)
 {
-    __shared__ float sh[256];
-    const int64_t j = blockIdx.x;
     const int t = threadIdx.x;
     T *col = Ah ? Ah + j * ldh : nullptr;
     if (j >= n) {  // padding column: e_j
@@ -151,6 +157,19 @@ __global__ __launch_bounds__(256) void k_heq_jac_round(int64_t n, int64_t Np, do
             col[i] = cvt_out<T>((float)v * s);
     }
     for (int64_t i = n + t; i < Np; i += 256) col[i] = cvt_out<T>(0.0f);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_heq_jac_round(int64_t n, int64_t Np, double c,
+                                                       const double *__restrict__ D,
+                                                       const double *__restrict__ h,
+                                                       float *__restrict__ J, int64_t ldj,
+                                                       T *__restrict__ Ah, int64_t ldh,
+                                                       float *__restrict__ colscale,
+                                                       float target_log2, int *flags)
+{
+    __shared__ float sh[256];
+    heq_jac_column<T>(blockIdx.x, n, Np, c, D, h, J, ldj, Ah, ldh, colscale, target_log2, flags, sh);
 }
 
 // Generic J (FP32) -> Ah rounding with optional column scaling.
@@ -397,6 +416,205 @@ __global__ __launch_bounds__(256) void k_pad_out(int64_t n, int64_t Np, const T 
 // --------------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+
+// ====================================================== batched engine kernels
+// Slot masks: bit (1 << phase) selects the slots a launch works on.
+
+// x = ones for freshly admitted slots
+__global__ __launch_bounds__(256) void k_b_fill_x0(const BDesc *__restrict__ d,
+                                                   const BState *__restrict__ st, int nslots)
+{
+    const int s = blockIdx.x;
+    if (s >= nslots || st[s].phase != BP_FRESH) return;
+    for (int64_t i = threadIdx.x; i < d[s].n; i += 256) d[s].x[i] = 1.0;
+    if (threadIdx.x == 0) d[s].flags[FLAG_FAIL] = 0;
+}
+
+// F(x), D(x) of eq. (3.2) for every selected slot; items are 16-row blocks
+__global__ __launch_bounds__(256) void k_b_residual(const BDesc *__restrict__ d,
+                                                    const BState *__restrict__ st, int nslots,
+                                                    int mask)
+{
+    __shared__ double red[HR][257];
+    __shared__ int off[B_MAX_SLOTS + 1];
+    const int total = b_offsets(nslots, off, [&](int s) {
+        return (mask >> st[s].phase & 1) ? (int)((d[s].n + HR - 1) / HR) : 0;
+    });
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = b_find(off, nslots, item);
+        const BDesc &q = d[s];
+        heq_residual_rows((int64_t)(item - off[s]) * HR, q.n, q.c, q.x, q.h, q.F, q.D, red);
+        __syncthreads();
+    }
+}
+
+// deterministic FP64 Euclidean norm of v[0 .. n) by one 256-thread block
+template <typename V>
+__device__ __forceinline__ double block_nrm2(int64_t n, const V *__restrict__ v, double *sh)
+{
+    const int t = threadIdx.x;
+    double a = 0.0;
+    for (int64_t i = t; i < n; i += 256) {
+        const double e = (double)v[i];
+        a += e * e;
+    }
+    sh[t] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    const double r = sqrt(sh[0]);
+    __syncthreads();
+    return r;
+}
+
+// ||F||, the stopping test of Algorithm 2.1 and the per-slot bookkeeping.
+// Fresh slots: F(x0) gives f0 and tau = tau_r f0 + tau_a.
+__global__ __launch_bounds__(256) void k_b_newton_check(const BDesc *__restrict__ d,
+                                                        BState *__restrict__ st, int nslots,
+                                                        int mask, BParams p)
+{
+    __shared__ double sh[256];
+    const int s = blockIdx.x;
+    if (s >= nslots || !(mask >> st[s].phase & 1)) return;
+    const double fn = block_nrm2(d[s].n, d[s].F, sh);
+    if (threadIdx.x != 0) return;
+    BState &q = st[s];
+    if (q.phase == BP_FRESH) {
+        q.f0 = fn;
+        q.tau = p.tau_r * fn + p.tau_a;
+        q.its = 0;
+        q.rel[0] = 1.0;
+        q.phase = BP_RUN;
+    } else {
+        q.rel[q.its] = q.f0 > 0.0 ? fn / q.f0 : 0.0;
+    }
+    q.fn = fn;
+    q.factor = 0;
+    if (!isfinite(fn)) {
+        q.phase = BP_DONE;
+        q.status = N3P_E_NONFINITE;
+    } else if (fn <= q.tau) {
+        q.phase = BP_DONE;
+        q.status = N3P_OK;
+    } else if (q.its >= p.maxit || q.its >= N3P_MAX_HIST - 1) {
+        q.phase = BP_DONE;
+        q.status = N3P_NOT_CONVERGED;
+    } else {
+        q.factor = 1;
+    }
+}
+
+// J (FP32) and the rounded, column-scaled factor copy, one column per item
+template <typename T>
+__global__ __launch_bounds__(256) void k_b_jac(const BDesc *__restrict__ d,
+                                               const BState *__restrict__ st, int nslots, float tl)
+{
+    __shared__ float sh[256];
+    __shared__ int off[B_MAX_SLOTS + 1];
+    const int total = b_offsets(nslots, off, [&](int s) {
+        return (st[s].phase == BP_RUN && st[s].factor) ? (int)d[s].Np : 0;
+    });
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = b_find(off, nslots, item);
+        const BDesc &q = d[s];
+        if (item == off[s] && threadIdx.x == 0) {
+            q.flags[FLAG_FAIL] = 0;
+            q.flags[FLAG_NONFINITE] = 0;
+        }
+        heq_jac_column<T>(item - off[s], q.n, q.Np, q.c, q.D, q.h, q.J, q.n, (T *)q.A, q.Np,
+                          q.colscale, tl, nullptr, sh);
+        __syncthreads();
+    }
+}
+
+// After the factorisation: unit right-hand side b = -F/||F|| (eq. (2.17)),
+// u = 0, r = b, and the IR state (Algorithm 2.2).  A slot whose matrix needs
+// row interchanges, or whose factors are not finite, ends here.
+__global__ __launch_bounds__(256) void k_b_ir_init(const BDesc *__restrict__ d,
+                                                   BState *__restrict__ st, int nslots, BParams p)
+{
+    __shared__ double sh[256];
+    const int s = blockIdx.x;
+    if (s >= nslots || st[s].phase != BP_RUN || !st[s].factor) return;
+    const BDesc &q = d[s];
+    const int t = threadIdx.x;
+    const int fail = ld_flag(&q.flags[FLAG_FAIL]), bad = ld_flag(&q.flags[FLAG_NONFINITE]);
+    if (fail || bad) {
+        if (t == 0) {
+            st[s].phase = BP_DONE;
+            st[s].status = fail ? N3P_E_PIVOTING : N3P_E_NONFINITE;
+            st[s].factor = 0;
+        }
+        return;
+    }
+    const double fn = st[s].fn;
+    for (int64_t i = t; i < q.Np; i += 256) {
+        const float v = i < q.n ? (float)(-q.F[i] / fn) : 0.0f;
+        q.b[i] = v;
+        q.r[i] = v;
+        q.u[i] = 0.0f;
+    }
+    __syncthreads();
+    const double nb = block_nrm2(q.Np, q.b, sh);
+    if (t == 0) {
+        BState &z = st[s];
+        z.nb = nb;
+        z.rn = nb;
+        z.sweeps = 0;
+        z.ir_failed = 0;
+        z.ir_on = (p.max_sweeps > 0 && !(nb < p.eta * nb)) ? 1 : 0;
+    }
+}
+
+// One IR sweep's bookkeeping: ||r||, growth test, success test, sweep cap.
+// On growth the previous iterate is restored (Section 3.1).
+__global__ __launch_bounds__(256) void k_b_ir_check(const BDesc *__restrict__ d,
+                                                    BState *__restrict__ st, int nslots, BParams p)
+{
+    __shared__ double sh[256];
+    __shared__ int grew;
+    const int s = blockIdx.x;
+    if (s >= nslots || st[s].phase != BP_RUN || !st[s].factor || !st[s].ir_on) return;
+    const BDesc &q = d[s];
+    const double rnew = block_nrm2(q.Np, q.r, sh);
+    if (threadIdx.x == 0) {
+        BState &z = st[s];
+        z.sweeps += 1;
+        grew = !(rnew <= z.rn);
+        if (grew) {
+            z.ir_failed = 1;
+            z.ir_on = 0;
+        } else {
+            z.rn = rnew;
+            z.ir_on = (!(z.rn < p.eta * z.nb) && z.sweeps < p.max_sweeps) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (grew)
+        for (int64_t i = threadIdx.x; i < q.Np; i += 256) q.u[i] = q.uprev[i];
+}
+
+// x += ||F|| u in FP64 (eq. (2.18)); close the step's bookkeeping
+__global__ __launch_bounds__(256) void k_b_ir_final(const BDesc *__restrict__ d,
+                                                    BState *__restrict__ st, int nslots, BParams p)
+{
+    const int s = blockIdx.x;
+    if (s >= nslots || st[s].phase != BP_RUN || !st[s].factor) return;
+    const BDesc &q = d[s];
+    const double fn = st[s].fn;
+    for (int64_t i = threadIdx.x; i < q.n; i += 256) q.x[i] += fn * (double)q.u[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        BState &z = st[s];
+        if (!z.ir_failed && !(z.rn < p.eta * z.nb)) z.ir_failed = 1;
+        z.lin[z.its] = z.sweeps;
+        z.its += 1;
+        z.factor = 0;
+    }
+}
+
 hipError_t launch_hinv(int64_t n, double *h, hipStream_t s)
 {
     hipLaunchKernelGGL(k_hinv, dim3(nblk(2 * n - 1, 256)), dim3(256), 0, s, 2 * n - 1, h);
@@ -605,6 +823,51 @@ hipError_t launch_f32_to_f64(int64_t n, const float *src, double *dst, hipStream
 hipError_t launch_f64_to_f32(int64_t n, const double *src, float *dst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_f64_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------- batched launchers
+hipError_t launch_b_fill_x0(const BDesc *d, const BState *st, int nslots, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_fill_x0, dim3(nslots), dim3(256), 0, s, d, st, nslots);
+    return hipGetLastError();
+}
+hipError_t launch_b_residual(const BDesc *d, BState *st, int nslots, int mask, int grid,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_residual, dim3(grid), dim3(256), 0, s, d, st, nslots, mask);
+    return hipGetLastError();
+}
+hipError_t launch_b_newton_check(const BDesc *d, BState *st, int nslots, int mask, BParams p,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_newton_check, dim3(nslots), dim3(256), 0, s, d, st, nslots, mask, p);
+    return hipGetLastError();
+}
+hipError_t launch_b_jac(int prec, const BDesc *d, BState *st, int nslots, float tl, int grid,
+                        hipStream_t s)
+{
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_b_jac<f16>, dim3(grid), dim3(256), 0, s, d, st, nslots, tl); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_b_jac<bf16>, dim3(grid), dim3(256), 0, s, d, st, nslots, tl); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_b_ir_init(const BDesc *d, BState *st, int nslots, BParams p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_ir_init, dim3(nslots), dim3(256), 0, s, d, st, nslots, p);
+    return hipGetLastError();
+}
+hipError_t launch_b_ir_check(const BDesc *d, BState *st, int nslots, BParams p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_ir_check, dim3(nslots), dim3(256), 0, s, d, st, nslots, p);
+    return hipGetLastError();
+}
+hipError_t launch_b_ir_final(const BDesc *d, BState *st, int nslots, BParams p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_ir_final, dim3(nslots), dim3(256), 0, s, d, st, nslots, p);
     return hipGetLastError();
 }
 

@@ -486,4 +486,147 @@ hipError_t launch_krylov_update(int64_t n, const float *V, int64_t ldv, int k, c
     return hipGetLastError();
 }
 
+
+// ====================================================== batched engine kernels
+// One workgroup per slot (N <= B_MAX_NP): y = L^{-1} r (unit lower), then
+// z = U^{-1} y, d = S z (S the FP16 column scale), and uprev = u, u += d:
+// the correction step of Algorithm 2.2 with the stored half-precision factors
+// promoted to FP32 as they are read (Section 2.3).  Blocked by 64: one wave
+// substitutes the diagonal block (a row per lane, readlane broadcasts), then
+// all waves update the remaining rows with coalesced column reads.
+template <typename T>
+__global__ __launch_bounds__(B_SOLVE_THREADS) void k_b_solve(const BDesc *__restrict__ d,
+                                                             const BState *__restrict__ st,
+                                                             int nslots)
+{
+    constexpr int NT = B_SOLVE_THREADS;
+    __shared__ float y[B_MAX_NP];
+    __shared__ float Dg[64][65];
+    const int s = blockIdx.x;
+    if (s >= nslots || st[s].phase != BP_RUN || !st[s].factor || !st[s].ir_on) return;
+    const BDesc &q = d[s];
+    const int64_t Np = q.Np, n = q.n;
+    const T *__restrict__ A = (const T *)q.A;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nb = (int)(Np / 64);
+    for (int64_t i = t; i < Np; i += NT) y[i] = q.r[i];
+    __syncthreads();
+    for (int blk = 0; blk < nb; ++blk) {  // forward, unit lower
+        const int64_t b0 = (int64_t)blk * 64;
+        for (int e = t; e < 4096; e += NT) {
+            const int i = e & 63, k = e >> 6;
+            Dg[i][k] = to_f32(A[(b0 + i) + (b0 + k) * Np]);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            float lr[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) lr[k] = lane > k ? Dg[lane][k] : 0.0f;
+            float yi = y[b0 + lane];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) yi -= lr[k] * lane_bcast(yi, k);
+            y[b0 + lane] = yi;
+        }
+        __syncthreads();
+        for (int64_t i = b0 + 64 + t; i < Np; i += NT) {
+            const T *__restrict__ col = A + i + b0 * Np;
+            float acc = y[i];
+#pragma unroll 16
+            for (int k = 0; k < 64; ++k) acc -= to_f32(col[(int64_t)k * Np]) * y[b0 + k];
+            y[i] = acc;
+        }
+        __syncthreads();
+    }
+    for (int blk = nb - 1; blk >= 0; --blk) {  // backward, upper
+        const int64_t b0 = (int64_t)blk * 64;
+        for (int e = t; e < 4096; e += NT) {
+            const int i = e & 63, k = e >> 6;
+            Dg[i][k] = to_f32(A[(b0 + i) + (b0 + k) * Np]);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            float ur[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) ur[k] = lane < k ? Dg[lane][k] : 0.0f;
+            const float rd = 1.0f / Dg[lane][lane];
+            float yi = y[b0 + lane];
+#pragma unroll
+            for (int k = 63; k >= 0; --k) {
+                if (lane == k) yi *= rd;
+                yi -= ur[k] * lane_bcast(yi, k);
+            }
+            y[b0 + lane] = yi;
+        }
+        __syncthreads();
+        for (int64_t i = t; i < b0; i += NT) {
+            const T *__restrict__ col = A + i + b0 * Np;
+            float acc = y[i];
+#pragma unroll 16
+            for (int k = 0; k < 64; ++k) acc -= to_f32(col[(int64_t)k * Np]) * y[b0 + k];
+            y[i] = acc;
+        }
+        __syncthreads();
+    }
+    for (int64_t i = t; i < Np; i += NT) {
+        float di = 0.0f;
+        if (i < n) di = q.colscale ? y[i] * q.colscale[i] : y[i];
+        const float ui = q.u[i];
+        q.uprev[i] = ui;
+        q.u[i] = ui + di;
+    }
+}
+
+// r = b - J u with FP64 accumulation; items are 256-row blocks of a slot
+__global__ __launch_bounds__(256) void k_b_gemv(const BDesc *__restrict__ d,
+                                                const BState *__restrict__ st, int nslots)
+{
+    __shared__ float us[B_MAX_NP];
+    __shared__ int off[B_MAX_SLOTS + 1];
+    const int total = b_offsets(nslots, off, [&](int s) {
+        return (st[s].phase == BP_RUN && st[s].factor && st[s].ir_on) ? (int)((d[s].Np + 255) / 256) : 0;
+    });
+    const int t = threadIdx.x;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = b_find(off, nslots, item);
+        const BDesc &q = d[s];
+        const int64_t n = q.n;
+        for (int64_t j = t; j < n; j += 256) us[j] = q.u[j];
+        __syncthreads();
+        const int64_t i = (int64_t)(item - off[s]) * 256 + t;
+        if (i < n) {
+            const float *__restrict__ row = q.J + i;
+            double acc = (double)q.b[i];
+            int64_t j = 0;
+            for (; j + 8 <= n; j += 8) {
+                float a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = row[(j + u) * n];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc -= (double)a[u] * (double)us[j + u];
+            }
+            for (; j < n; ++j) acc -= (double)row[j * n] * (double)us[j];
+            q.r[i] = (float)acc;
+        } else if (i < q.Np) {
+            q.r[i] = 0.0f;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_b_solve(int prec, const BDesc *d, const BState *st, int nslots, hipStream_t s)
+{
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_b_solve<f16>, dim3(nslots), dim3(B_SOLVE_THREADS), 0, s, d, st, nslots); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_b_solve<bf16>, dim3(nslots), dim3(B_SOLVE_THREADS), 0, s, d, st, nslots); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_b_gemv(const BDesc *d, const BState *st, int nslots, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_gemv, dim3(grid), dim3(256), 0, s, d, st, nslots);
+    return hipGetLastError();
+}
+
 }  // namespace n3p

@@ -499,6 +499,7 @@ N3P_API const char *n3p_status_str(int st)
     case N3P_E_CALLBACK: return "N3P_E_CALLBACK";
     case N3P_E_HIP: return "N3P_E_HIP";
     case N3P_E_TIMEOUT: return "N3P_E_TIMEOUT";
+    case N3P_E_PIVOTING: return "N3P_E_PIVOTING";
     default: return "N3P_UNKNOWN";
     }
 }

@@ -205,4 +205,96 @@ hipError_t launch_krylov_update(int64_t n, const float *V, int64_t ldv, int k, c
 
 size_t trsv_sync_ints(int64_t n);
 
+
+// ============================================================ batched engine
+// Many independent H-equation solves advance together, one Newton step per
+// round: every kernel below walks a table of slots.  BDesc is written by the
+// host when a request is admitted; BState is written only by the kernels and
+// read back by the host after each step.  A slot's arithmetic never depends on
+// which other slots are present (no reductions across slots), so a request's
+// result is the same alone and in any mix.
+constexpr int B_LEAF = NB_LEAF;      // leaf width and padding granule (64)
+constexpr int B_MAX_NP = 4096;       // largest padded size of a batched solve
+constexpr int B_SOLVE_THREADS = 1024;
+
+constexpr int B_MAX_SLOTS = 256;
+
+enum BPhase { BP_FREE = 0, BP_FRESH = 1, BP_RUN = 2, BP_DONE = 3 };
+
+// Work items of a batched launch: slot s contributes cnt(s) items.  Every
+// workgroup builds the same prefix table in LDS (off[0 .. nslots]) and walks
+// items blockIdx.x, blockIdx.x + gridDim.x, ...  b_find returns the slot of an
+// item (the largest s with off[s] <= item, which skips empty slots).
+template <typename Cnt>
+__device__ __forceinline__ int b_offsets(int nslots, int *off, Cnt cnt)
+{
+    for (int t = threadIdx.x; t < nslots; t += blockDim.x) off[t + 1] = cnt(t);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        off[0] = 0;
+        for (int i = 0; i < nslots; ++i) off[i + 1] += off[i];
+    }
+    __syncthreads();
+    return off[nslots];
+}
+__device__ __forceinline__ int b_find(const int *off, int nslots, int item)
+{
+    int lo = 0, hi = nslots - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct BDesc {
+    int64_t n, Np;
+    double c;
+    int prec;            // N3P_FP16 or N3P_BF16
+    int pad_;
+    void *A;             // factor buffer, Np x Np column-major (ld Np), identity padding
+    void *LT;            // L of the current leaf, transposed: row i at LT + 64 i
+    void *DG;            // 2 x 64 x 64 factored diagonal blocks
+    float *J;            // n x n FP32 Jacobian, ld n
+    float *colscale;     // Np
+    double *x, *F, *D, *h;          // n, n, n, 2n
+    float *b, *u, *uprev, *r, *y;   // Np each
+    int *flags;          // NFLAGS
+};
+
+struct BState {
+    int phase, status, its, factor;
+    int ir_on, sweeps, ir_failed, pad_;
+    double f0, fn, tau, nb, rn;
+    double rel[N3P_MAX_HIST];        // ||F_k|| / ||F_0||
+    int lin[N3P_MAX_HIST];           // IR sweeps at step k+1
+};
+
+struct BParams {                     // per-engine constants
+    double tau_r, tau_a, eta;
+    int maxit, max_sweeps;
+    float target_log2;
+    int pad_;
+};
+
+// launchers (grid sizes are the engine's, from its tuning table)
+hipError_t launch_b_residual(const BDesc *d, BState *st, int nslots, int phase_mask, int grid,
+                             hipStream_t s);
+hipError_t launch_b_newton_check(const BDesc *d, BState *st, int nslots, int phase_mask,
+                                 BParams p, hipStream_t s);
+hipError_t launch_b_jac(int prec, const BDesc *d, BState *st, int nslots, float tl, int grid,
+                        hipStream_t s);
+hipError_t launch_b_leaf(int prec, const BDesc *d, const BState *st, int nslots, int leaf,
+                         int grid, hipStream_t s);
+hipError_t launch_b_gemm(int prec, const BDesc *d, const BState *st, int nslots, int leaf,
+                         int kc, int grid, hipStream_t s);
+hipError_t launch_b_ir_init(const BDesc *d, BState *st, int nslots, BParams p, hipStream_t s);
+hipError_t launch_b_solve(int prec, const BDesc *d, const BState *st, int nslots,
+                          hipStream_t s);
+hipError_t launch_b_gemv(const BDesc *d, const BState *st, int nslots, int grid, hipStream_t s);
+hipError_t launch_b_ir_check(const BDesc *d, BState *st, int nslots, BParams p, hipStream_t s);
+hipError_t launch_b_ir_final(const BDesc *d, BState *st, int nslots, BParams p, hipStream_t s);
+hipError_t launch_b_fill_x0(const BDesc *d, const BState *st, int nslots, hipStream_t s);
+
 }  // namespace n3p
