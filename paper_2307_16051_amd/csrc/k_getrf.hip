@@ -391,27 +391,30 @@ __device__ __forceinline__ void gemm16_tile(int row0, int col0, int K, const T *
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[a][b][q] = 0.0f;
 
-    uint4 ra[ACH], rb[BCH];
+    // staging registers as native vectors (a union-based vector type would be
+    // kept in scratch or LDS by the compiler)
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 ra[ACH], rb[BCH];
 #define N3P_GLOAD(kk_)                                                                        \
     do {                                                                                      \
         _Pragma("unroll") for (int c = 0; c < ACH; ++c) {                                     \
             const int ch = tid + c * NT, r = ch / CPR, seg = ch % CPR;                        \
-            ra[c] = *(const uint4 *)(At + (int64_t)(row0 + r) * ldat + (kk_) + seg * 8);      \
+            ra[c] = *(const u32x4 *)(At + (int64_t)(row0 + r) * ldat + (kk_) + seg * 8);      \
         }                                                                                     \
         _Pragma("unroll") for (int c = 0; c < BCH; ++c) {                                     \
             const int ch = tid + c * NT, r = ch / CPR, seg = ch % CPR;                        \
-            rb[c] = *(const uint4 *)(B + (int64_t)(col0 + r) * ldb + (kk_) + seg * 8);        \
+            rb[c] = *(const u32x4 *)(B + (int64_t)(col0 + r) * ldb + (kk_) + seg * 8);        \
         }                                                                                     \
     } while (0)
 #define N3P_SSTORE(buf_)                                                                      \
     do {                                                                                      \
         _Pragma("unroll") for (int c = 0; c < ACH; ++c) {                                     \
             const int ch = tid + c * NT, r = ch / CPR, seg = ch % CPR;                        \
-            *(uint4 *)(&As[(buf_)][r * KP + seg * 8]) = ra[c];                                \
+            *(u32x4 *)(&As[(buf_)][r * KP + seg * 8]) = ra[c];                                \
         }                                                                                     \
         _Pragma("unroll") for (int c = 0; c < BCH; ++c) {                                     \
             const int ch = tid + c * NT, r = ch / CPR, seg = ch % CPR;                        \
-            *(uint4 *)(&Bs[(buf_)][r * KP + seg * 8]) = rb[c];                                \
+            *(u32x4 *)(&Bs[(buf_)][r * KP + seg * 8]) = rb[c];                                \
         }                                                                                     \
     } while (0)
 
@@ -482,10 +485,17 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
     const int ntm = M / TM, ntn = N / TN, nt = ntm * ntn;
     const int bid = blockIdx.x;
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs;
-    // give each XCD a contiguous run of tiles (shared B columns stay in its L2)
-    int tile = bid;
-    if ((nt & 7) == 0) tile = (bid & 7) * (nt >> 3) + (bid >> 3);
-    const int tm = tile % ntm, tn = tile / ntm;
+    // give each XCD a contiguous run of tiles, and order that run in groups
+    // of GM row tiles so the tiles an XCD's CUs hold at once share a few A
+    // row blocks and B column blocks in its L2.
+    // workgroup bid runs on XCD bid % 8; XCD x owns tiles [start_x, start_x + count_x)
+    const int xcd = bid & 7, q8 = nt >> 3, r8 = nt & 7;
+    const int tile = xcd * q8 + (xcd < r8 ? xcd : r8) + (bid >> 3);
+    constexpr int GM = 8;
+    const int per_group = GM * ntn, group = tile / per_group, first_m = group * GM;
+    const int gsize = ntm - first_m < GM ? ntm - first_m : GM;
+    const int in_group = tile - group * per_group;
+    const int tm = first_m + in_group % gsize, tn = in_group / gsize;
     gemm16_tile<T, TM, TN, WGM, WGN, KC>(tm * TM, tn * TN, K, At, ldat, B, ldb, C, ldc, flags);
 }
 
