@@ -183,6 +183,22 @@ def main():
                      "traffic": None, "kernel": "getrf (whole factorisation, (2/3)N^3 flop)",
                      "padded_n": Np},
     }
+    # the same solve with the O(N log N) residual and operator-based J v
+    # (no stored FP32 Jacobian), for comparison
+    opts_mf = n3p.Options.default(fft_residual=1, matrix_free=1)
+    ws_mf = torch.empty(n3p.workspace_size(n, prec, solver, opts_mf), dtype=torch.uint8, device=dev)
+    x.fill_(1.0)
+    n3p.solve_heq(n, c, x=x, prec=prec, solver=solver, opts=opts_mf, ws=ws_mf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x.fill_(1.0)
+    _, rep_mf = n3p.solve_heq(n, c, x=x, prec=prec, solver=solver, opts=opts_mf, ws=ws_mf)
+    torch.cuda.synchronize()
+    out["fft_matrix_free"] = {"ms": (time.perf_counter() - t0) * 1e3, "its": rep_mf.its,
+                              "linear_solve_ms": rep_mf.ms_solve, "residual_ms": rep_mf.ms_resid,
+                              "workspace_gib": ws_mf.numel() / 2 ** 30,
+                              "workspace_gib_stored_J": ws.numel() / 2 ** 30}
+    del ws_mf
     if not args.no_fp64:
         opts64 = n3p.Options.default()
         ws64 = torch.empty(n3p.workspace_size(n, n3p.FP64, n3p.DIRECT, opts64), dtype=torch.uint8,

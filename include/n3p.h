@@ -106,6 +106,14 @@ typedef struct n3p_options {
     int scale_mode;          /* n3p_scale (default N3P_SCALE_AUTO) */
     int timing;              /* 1: record per-phase times in the report (adds
                                 event records; default 1) */
+    int fft_residual;        /* built-in H-equation only: 1 = evaluate F by the
+                                O(N log N) FFT form of eq. (3.2) (the Hankel sum as
+                                a convolution, FP64); N <= 32768; default 0 */
+    int matrix_free;         /* built-in H-equation only: 1 = the IR residual and the
+                                GMRES products J v are formed from the operator
+                                (J v = v - diag(1/D^2) K v by FFT in FP64, rounded to
+                                FP32) instead of the stored FP32 J, which is then not
+                                formed (4 N^2 fewer bytes); N <= 32768; default 0 */
 } n3p_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -267,6 +275,20 @@ N3P_API int n3p_gmres_ir(int prec, int64_t n, const float *A, int64_t lda, const
 /* Workspace bytes for n3p_ir / n3p_gmres_ir / n3p_gemv_resid_f32 at size n
  * with Krylov dimension m (ignored for IR). */
 N3P_API size_t n3p_linsolve_workspace_size(int64_t n, int m);
+
+/* FFT form of the H-equation (eq. (3.2); the cost model of Section 3).  The
+ * Hankel sum S_i = sum_j x_j / (i + j + 1) is a convolution, evaluated with a
+ * complex FP64 FFT of length L = 2^p >= 2N - 1 (N <= 32768).  Device pointers;
+ * ws: device workspace of n3p_heq_fft_workspace_size(n) bytes.  Each call
+ * also prepares the twiddles and the transform of the kernel (O(L log L)). */
+N3P_API size_t n3p_heq_fft_workspace_size(int64_t n);
+/* F (and D if non-null), FP64, as n3p_heq_residual. */
+N3P_API int n3p_heq_residual_fft(int64_t n, double c, const double *x, double *F, double *D,
+                                 void *ws, size_t ws_bytes, void *stream);
+/* y = J v with J = I - diag(1/D^2) K (eq. (3.2)), computed in FP64 from the FP32
+ * vector v and rounded to FP32; D from the residual at the current iterate. */
+N3P_API int n3p_heq_jv(int64_t n, double c, const double *D, const float *v, float *y, void *ws,
+                       size_t ws_bytes, void *stream);
 
 /* ===================================================== batched engine (serving)
  * Many independent H-equation solves (eq. (3.2), x0 = ones) advance through

@@ -16,5 +16,5 @@ from ._binding import (  # noqa: F401
     workspace_size, solve_heq, solve_dense_tanh, solve,
     getrf, getrs, gemv_resid, heq_residual, heq_jacobian, ir, gmres_ir,
     EngineConfig, ServeStats, Engine, serve, engine_request_bytes, engine_fixed_bytes,
-    PHASE_FREE, PHASE_ADMITTED, PHASE_RUNNING, PHASE_DONE,
+    PHASE_FREE, PHASE_ADMITTED, PHASE_RUNNING, PHASE_DONE, heq_residual_fft, heq_jv,
 )

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
     _fields_ = [("tau_r", _f64), ("tau_a", _f64), ("tau_abs_override", _f64), ("eta", _f64),
                 ("maxit", _int), ("max_ir_sweeps", _int), ("gmres_restart", _int),
                 ("gmres_tol", _f64), ("gmres_max_restarts", _int), ("scale_mode", _int),
-                ("timing", _int)]
+                ("timing", _int), ("fft_residual", _int), ("matrix_free", _int)]
 
     @classmethod
     def default(cls, **kw) -> "Options":
@@ -469,3 +469,38 @@ def serve(ns, cs, arrivals, pool: torch.Tensor, cfg: Optional[EngineConfig] = No
                        its, status, lat, ctypes.byref(stats), _stream())
     _check(st, "n3p_serve")
     return list(its), list(status), list(lat), stats.as_dict()
+
+
+# ------------------------------------------------------ FFT form of eq. (3.2)
+def _setup_fft():
+    L = lib
+    L.n3p_heq_fft_workspace_size.argtypes = [_i64]
+    L.n3p_heq_fft_workspace_size.restype = ctypes.c_size_t
+    L.n3p_heq_residual_fft.argtypes = [_i64, _f64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.n3p_heq_residual_fft.restype = _int
+    L.n3p_heq_jv.argtypes = [_i64, _f64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.n3p_heq_jv.restype = _int
+
+
+_setup_fft()
+
+
+def heq_residual_fft(x: torch.Tensor, c: float):
+    """(F, D) of eq. (3.2) by the O(N log N) FFT form (FP64 device tensors)."""
+    n = x.numel()
+    F = torch.empty_like(x)
+    D = torch.empty_like(x)
+    ws = _ws(lib.n3p_heq_fft_workspace_size(n), x.device)
+    _check(lib.n3p_heq_residual_fft(n, c, _ptr(x), _ptr(F), _ptr(D), _ptr(ws), ws.numel(),
+                                    _stream()), "n3p_heq_residual_fft")
+    return F, D
+
+
+def heq_jv(D: torch.Tensor, v: torch.Tensor, c: float) -> torch.Tensor:
+    """J v for eq. (3.2) from the operator (FP64 compute, FP32 result)."""
+    n = v.numel()
+    y = torch.empty(n, dtype=torch.float32, device=v.device)
+    ws = _ws(lib.n3p_heq_fft_workspace_size(n), v.device)
+    _check(lib.n3p_heq_jv(n, c, _ptr(D), _ptr(v), _ptr(y), _ptr(ws), ws.numel(), _stream()),
+           "n3p_heq_jv")
+    return y

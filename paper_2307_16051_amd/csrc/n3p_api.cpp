@@ -233,6 +233,10 @@ struct SolveWs {
     double *H = nullptr, *ydev = nullptr;
     double *b64 = nullptr, *y64 = nullptr, *x64 = nullptr, *xs64 = nullptr;
     int *sync = nullptr;
+    // FFT form of the H-equation (fft_residual / matrix_free)
+    int L = 0;
+    bool fftres = false, mf = false;
+    double2 *tw = nullptr, *Hh = nullptr, *t1 = nullptr, *t2 = nullptr, *W = nullptr;
     size_t bytes = 0;
 };
 
@@ -242,13 +246,15 @@ size_t part_len_for(int64_t n)
     return (size_t)std::max<int64_t>(256, n * ((n + 255) / 256));
 }
 
-size_t solve_layout(int64_t n, int prec, int ls, int m, SolveWs *w, char *base)
+size_t solve_layout(int64_t n, int prec, int ls, int m, int fftmode, SolveWs *w, char *base)
 {
+    // fftmode: bit 0 FFT residual, bit 1 matrix-free J v (no stored FP32 J)
     Bump b;
     const int64_t Np = padded(n);
     FactorWs f;
     factor_bytes(prec, Np, b, &f, base);
-    size_t oJ = b.take((size_t)n * n * 4);
+    const bool mf = (fftmode & 2) != 0;
+    size_t oJ = mf ? 0 : b.take((size_t)n * n * 4);
     size_t oCS = b.take((size_t)Np * 4);
     size_t oF = b.take((size_t)n * 8), oD = b.take((size_t)n * 8), oH = b.take((size_t)2 * n * 8);
     const size_t pl = part_len_for(n);
@@ -271,14 +277,33 @@ size_t solve_layout(int64_t n, int prec, int ls, int m, SolveWs *w, char *base)
         oxs64 = b.take((size_t)Np * 8);
     }
     size_t osync = b.take(trsv_sync_ints(Np) * 4);
+    const int L = fftmode ? fft_length(n) : 0;
+    size_t otw = 0, oHf = 0, ot1 = 0, ot2 = 0, oW = 0;
+    if (L) {
+        otw = b.take((size_t)L * 16);
+        oHf = b.take((size_t)L * 16);
+        ot1 = b.take((size_t)L * 16);
+        ot2 = b.take((size_t)L * 16);
+        oW = b.take((size_t)L * 16);
+    }
     if (w && base) {
+        w->L = L;
+        w->fftres = L && (fftmode & 1);
+        w->mf = L && mf;
+        if (L) {
+            w->tw = (double2 *)(base + otw);
+            w->Hh = (double2 *)(base + oHf);
+            w->t1 = (double2 *)(base + ot1);
+            w->t2 = (double2 *)(base + ot2);
+            w->W = (double2 *)(base + oW);
+        }
         w->n = n;
         w->Np = Np;
         w->prec = prec;
         w->ls = ls;
         w->m = m;
         w->f = f;
-        w->J = (float *)(base + oJ);
+        w->J = mf ? nullptr : (float *)(base + oJ);
         w->colscale = (float *)(base + oCS);
         w->F = (double *)(base + oF);
         w->D = (double *)(base + oD);
@@ -346,7 +371,33 @@ struct LinCtx {
     int *flags;
     Epoch *epoch;
     hipStream_t s;
+    // matrix-free J v of the H-equation (null tw: use the stored A)
+    const double2 *tw, *Hh;
+    double2 *t1, *t2, *W;
+    const double *D;
+    double c;
+    int L;
 };
+
+// r = b - A u  (A stored FP32, or the H-equation operator when matrix-free)
+int lin_resid(LinCtx &c, const float *u, const float *b, float *r, double *part)
+{
+    if (c.tw)
+        HIPCHK(launch_hk_jv(c.n, c.n, c.L, c.c, c.D, u, b, r, c.tw, c.Hh, c.t1, c.t2, c.W, c.s));
+    else
+        HIPCHK(launch_gemv_resid(c.n, c.A, c.lda, u, b, r, part, c.s));
+    return 0;
+}
+
+// y = A v
+int lin_matvec(LinCtx &c, const float *v, float *y)
+{
+    if (c.tw)
+        HIPCHK(launch_hk_jv(c.n, c.n, c.L, c.c, c.D, v, nullptr, y, c.tw, c.Hh, c.t1, c.t2, c.W, c.s));
+    else
+        HIPCHK(launch_gemv_f32(c.n, c.A, c.lda, v, y, c.part, c.s));
+    return 0;
+}
 
 // out = S U^{-1} L^{-1} P in   (the preconditioner-vector product)
 int apply_prec(LinCtx &c, const float *in, float *out)
@@ -394,7 +445,7 @@ int gmres_lp(LinCtx &c, const float *r, float *d, int m, double rtol, int max_re
         int k_used = 0;
         bool conv = false;
         for (int j = 0; j < m; ++j) {
-            HIPCHK(launch_gemv_f32(n, c.A, c.lda, c.V + (int64_t)j * c.ldv, c.av, c.part, c.s));
+            CHK(lin_matvec(c, c.V + (int64_t)j * c.ldv, c.av));
             CHK(apply_prec(c, c.av, c.w));
             HIPCHK(launch_mgs(n, c.V, c.ldv, j, c.w, c.H, c.s));
             HIPCHK(hipMemcpyAsync(hcol.data(), c.H, (size_t)(j + 2) * sizeof(double),
@@ -428,7 +479,7 @@ int gmres_lp(LinCtx &c, const float *r, float *d, int m, double rtol, int max_re
         HIPCHK(launch_krylov_update(n, c.V, c.ldv, k_used, c.ydev, d, c.s));
         if (conv || rs + 1 == max_restarts) break;
         // z = M^{-1} (r - A d) for the next cycle
-        HIPCHK(launch_gemv_resid(n, c.A, c.lda, d, r, c.av, c.part, c.s));
+        CHK(lin_resid(c, d, r, c.av, c.part));
         CHK(apply_prec(c, c.av, c.z));
     }
     HIPCHK(hipStreamSynchronize(c.s));
@@ -449,7 +500,7 @@ int refine(LinCtx &c, const float *b, float *u, double tol, int max_sweeps, bool
         HIPCHK(launch_fill_f32(u, 0.0f, c.n, c.s));
         HIPCHK(launch_vcopy_f32(c.n, c.r, b, c.s));
     } else {
-        HIPCHK(launch_gemv_resid(c.n, c.A, c.lda, u, b, c.r, c.part, c.s));
+        CHK(lin_resid(c, u, b, c.r, c.part));
         CHK(norm32(c, c.r, &rn));
     }
     o->sweeps = 0;
@@ -466,7 +517,7 @@ int refine(LinCtx &c, const float *b, float *u, double tol, int max_sweeps, bool
         }
         HIPCHK(launch_vcopy_f32(c.n, c.uprev, u, c.s));
         HIPCHK(launch_axpy_f32(c.n, u, c.d, 1.0f, c.s));
-        HIPCHK(launch_gemv_resid(c.n, c.A, c.lda, u, b, c.r, c.part, c.s));
+        CHK(lin_resid(c, u, b, c.r, c.part));
         double rnew = 0.0;
         CHK(norm32(c, c.r, &rnew));
         o->sweeps++;
@@ -520,6 +571,8 @@ N3P_API void n3p_default_options(n3p_options *o)
     o->gmres_max_restarts = 10;
     o->scale_mode = N3P_SCALE_AUTO;
     o->timing = 1;
+    o->fft_residual = 0;
+    o->matrix_free = 0;
 }
 
 N3P_API int n3p_problem_heq(n3p_problem *p, int64_t n, double c)
@@ -563,16 +616,27 @@ static int opt_m(const n3p_options *o)
     return o ? std::max(1, std::min(64, o->gmres_restart)) : 20;
 }
 
+static int fft_mode(const n3p_options *opt)
+{
+    return opt ? ((opt->fft_residual ? 1 : 0) | (opt->matrix_free ? 2 : 0)) : 0;
+}
+
 N3P_API size_t n3p_workspace_size(int64_t n, int lu_prec, int ls, const n3p_options *opt)
 {
     if (n < 1 || !valid_prec(lu_prec) || ls < N3P_IR || ls > N3P_DIRECT) return 0;
-    return solve_layout(n, lu_prec, ls, opt_m(opt), nullptr, nullptr);
+    if (fft_mode(opt) && !fft_length(n)) return 0;
+    return solve_layout(n, lu_prec, ls, opt_m(opt), fft_mode(opt), nullptr, nullptr);
 }
 
 static int eval_residual(const n3p_problem *p, const SolveWs &w, const double *x, hipStream_t s)
 {
     switch (p->kind) {
-    case 0: HIPCHK(launch_heq_residual(w.n, p->c, x, w.h, w.F, w.D, s)); break;
+    case 0:
+        if (w.fftres)
+            HIPCHK(launch_hk_residual(w.n, w.L, p->c, x, w.tw, w.Hh, w.t1, w.t2, w.W, w.F, w.D, s));
+        else
+            HIPCHK(launch_heq_residual(w.n, p->c, x, w.h, w.F, w.D, s));
+        break;
     case 1: HIPCHK(launch_dense_tanh_residual(w.n, p->A, p->lda, p->b, x, w.F, w.part, s)); break;
     case 2:
         if (p->residual(p->ctx, x, w.F, w.n, (void *)s) != 0) return N3P_E_CALLBACK;
@@ -622,11 +686,13 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
         opt.maxit < 0 || opt.maxit >= N3P_MAX_HIST || opt.max_ir_sweeps < 1)
         return N3P_E_INVALID;
     const int m = opt_m(&opt);
-    const size_t need = solve_layout(p->n, lu_prec, ls, m, nullptr, nullptr);
+    const int fm = fft_mode(&opt);
+    if (fm && (p->kind != 0 || !fft_length(p->n))) return N3P_E_INVALID;
+    const size_t need = solve_layout(p->n, lu_prec, ls, m, fm, nullptr, nullptr);
     if (ws_bytes < need) return N3P_E_NOMEM;
     char *base = (char *)(((uintptr_t)ws + ALIGN - 1) / ALIGN * ALIGN);
     SolveWs w;
-    solve_layout(p->n, lu_prec, ls, m, &w, base);
+    solve_layout(p->n, lu_prec, ls, m, fm, &w, base);
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = w.n;
 
@@ -659,6 +725,7 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
     HIPCHK(launch_fill_i32(w.sync, 0, (int64_t)trsv_sync_ints(w.Np), s));
     HIPCHK(launch_fill_i32(w.f.flags, 0, NFLAGS, s));
     if (p->kind == 0) HIPCHK(launch_hinv(n, w.h, s));
+    if (w.L) HIPCHK(launch_hk_setup(n, w.L, w.tw, w.Hh, w.t1, w.t2, s));
 
     int status = N3P_OK;
     double fn = 0.0;
@@ -704,6 +771,16 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
     lc.flags = w.f.flags;
     lc.epoch = &epoch;
     lc.s = s;
+    if (w.mf) {
+        lc.tw = w.tw;
+        lc.Hh = w.Hh;
+        lc.t1 = w.t1;
+        lc.t2 = w.t2;
+        lc.W = w.W;
+        lc.D = w.D;
+        lc.c = p->c;
+        lc.L = w.L;
+    }
 
     while (fn > tau && its < opt.maxit) {
         // --- J = F'(x) stored FP32, J_h = I_s^h(J) (column scaled for FP16)
@@ -718,7 +795,8 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
             auto refill = [&]() -> int {
                 // the FP64 factorisation of a built-in problem takes the FP64
                 // Jacobian again (J holds only its FP32 rounding)
-                if (w.prec == N3P_FP64 && p->kind != 2) return build_jacobian(p, w, x, tl, scaled, s);
+                if ((w.prec == N3P_FP64 || w.mf) && p->kind != 2)
+                    return build_jacobian(p, w, x, tl, scaled, s);
                 HIPCHK(launch_round_scale(w.prec, n, w.Np, w.J, n, w.f.A, w.Np,
                                           scaled ? w.colscale : nullptr, tl, w.f.flags, s));
                 return 0;
@@ -757,7 +835,7 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
                 CHK(apply_prec(lc, w.b, w.u));
                 lo.sweeps = 1;
                 lo.inner = 1;
-                HIPCHK(launch_gemv_resid(n, w.J, n, w.u, w.b, w.r, w.part, s));
+                CHK(lin_resid(lc, w.u, w.b, w.r, w.part));
                 double rn = 0, nb = 0;
                 CHK(norm32(lc, w.r, &rn));
                 CHK(norm32(lc, w.b, &nb));
@@ -997,6 +1075,59 @@ static int lin_common(int prec, int64_t n, const float *A, int64_t lda, const vo
     c->colscale = colscale;
     c->epoch = ep;
     c->s = s;
+    return 0;
+}
+
+N3P_API size_t n3p_heq_fft_workspace_size(int64_t n)
+{
+    const int L = n >= 1 ? fft_length(n) : 0;
+    return L ? (size_t)5 * L * sizeof(double2) + 5 * ALIGN : 0;
+}
+
+namespace {
+struct FftWs {
+    int L = 0;
+    double2 *tw = nullptr, *H = nullptr, *t1 = nullptr, *t2 = nullptr, *W = nullptr;
+};
+int fft_ws(int64_t n, void *ws, size_t bytes, FftWs *f)
+{
+    const size_t need = n3p_heq_fft_workspace_size(n);
+    if (!need) return N3P_E_INVALID;
+    if (!ws || bytes < need) return N3P_E_NOMEM;
+    Bump b;
+    char *base = (char *)(((uintptr_t)ws + ALIGN - 1) / ALIGN * ALIGN);
+    f->L = fft_length(n);
+    const size_t sz = (size_t)f->L * sizeof(double2);
+    f->tw = (double2 *)(base + b.take(sz));
+    f->H = (double2 *)(base + b.take(sz));
+    f->t1 = (double2 *)(base + b.take(sz));
+    f->t2 = (double2 *)(base + b.take(sz));
+    f->W = (double2 *)(base + b.take(sz));
+    return 0;
+}
+}  // namespace
+
+N3P_API int n3p_heq_residual_fft(int64_t n, double c, const double *x, double *F, double *D,
+                                 void *ws, size_t ws_bytes, void *stream)
+{
+    if (n < 1 || !x || !F) return N3P_E_INVALID;
+    FftWs f;
+    CHK(fft_ws(n, ws, ws_bytes, &f));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_hk_setup(n, f.L, f.tw, f.H, f.t1, f.t2, s));
+    HIPCHK(launch_hk_residual(n, f.L, c, x, f.tw, f.H, f.t1, f.t2, f.W, F, D, s));
+    return 0;
+}
+
+N3P_API int n3p_heq_jv(int64_t n, double c, const double *D, const float *v, float *y, void *ws,
+                       size_t ws_bytes, void *stream)
+{
+    if (n < 1 || !D || !v || !y) return N3P_E_INVALID;
+    FftWs f;
+    CHK(fft_ws(n, ws, ws_bytes, &f));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_hk_setup(n, f.L, f.tw, f.H, f.t1, f.t2, s));
+    HIPCHK(launch_hk_jv(n, n, f.L, c, D, v, nullptr, y, f.tw, f.H, f.t1, f.t2, f.W, s));
     return 0;
 }
 

@@ -206,6 +206,18 @@ hipError_t launch_krylov_update(int64_t n, const float *V, int64_t ldv, int k, c
 size_t trsv_sync_ints(int64_t n);
 
 
+// ------------------------------------------------ FFT form of the H-equation
+int fft_length(int64_t n);  // power of two >= 2n - 1 (0 if n > 32768)
+hipError_t launch_hk_setup(int64_t n, int L, double2 *tw, double2 *H, double2 *t1, double2 *t2,
+                           hipStream_t s);
+hipError_t launch_hk_residual(int64_t n, int L, double c, const double *x, const double2 *tw,
+                              const double2 *H, double2 *t1, double2 *t2, double2 *W, double *F,
+                              double *D, hipStream_t s);
+// out = b - J v (b non-null) or J v, rows n .. np-1 of out set to 0
+hipError_t launch_hk_jv(int64_t n, int64_t np, int L, double c, const double *D, const float *v,
+                        const float *b, float *out, const double2 *tw, const double2 *H,
+                        double2 *t1, double2 *t2, double2 *W, hipStream_t s);
+
 // ============================================================ batched engine
 // Many independent H-equation solves advance together, one Newton step per
 // round: every kernel below walks a table of slots.  BDesc is written by the

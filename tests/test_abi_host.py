@@ -74,3 +74,15 @@ def test_problem_setup_validates_arguments():
     assert B.lib.n3p_problem_heq(ctypes.byref(p), 10, 1.5) == -1
     assert B.lib.n3p_problem_dense_tanh(ctypes.byref(p), 10, None, 10, None) == -1
     assert n3p.status_str(-1) == "N3P_E_INVALID"
+
+
+def test_matrix_free_workspace_drops_the_fp32_jacobian():
+    """matrix_free: the stored FP32 J (4 N^2 bytes) is not part of the workspace."""
+    import paper_2307_16051_amd as n3p
+    n = 4096
+    full = n3p.workspace_size(n, n3p.FP16, n3p.IR, n3p.Options.default())
+    mf = n3p.workspace_size(n, n3p.FP16, n3p.IR, n3p.Options.default(matrix_free=1))
+    fft_bufs = 5 * 16 * 8192 + 5 * 256
+    assert abs((full - mf) - (4 * n * n - fft_bufs)) <= 2048
+    # the FFT form is limited to N <= 32768
+    assert n3p.workspace_size(40000, n3p.FP16, n3p.IR, n3p.Options.default(fft_residual=1)) == 0
