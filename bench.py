@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-LU Newton comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
+    ap.add_argument("--no-mf", action="store_true",
+                    help="skip the FFT / matrix-free comparison solve")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one plain 256 MiB device copy first (calibrates HBM byte counters)")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: seeded Poisson stream through the batched engine")
     ap.add_argument("--requests", type=int, default=2000)
@@ -132,6 +136,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calib:  # 256 MiB read + 256 MiB written by one copy kernel
+        src = torch.ones(2 ** 26, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n, c = args.n, args.c
     prec, solver = getattr(n3p, args.prec), getattr(n3p, args.solver)
     opts = n3p.Options.default()
@@ -180,11 +190,21 @@ def main():
                      if args.prec in ("FP16", "BF16") else PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / (PEAK_FP16_TFLOPS if args.prec in
                                                           ("FP16", "BF16") else PEAK_FP64_TFLOPS),
-                     "traffic": None, "kernel": "getrf (whole factorisation, (2/3)N^3 flop)",
-                     "padded_n": Np},
+                     "traffic": measured_traffic(n, args.prec),
+                     "kernel": "getrf (whole factorisation, (2/3)N^3 flop)", "padded_n": Np},
     }
     # the same solve with the O(N log N) residual and operator-based J v
     # (no stored FP32 Jacobian), for comparison
+    if not args.no_mf:
+        measure_matrix_free(n3p, torch, dev, n, c, prec, solver, x, ws, out)
+    if not args.no_fp64:
+        fp64_baseline(n3p, torch, dev, n, c, x, getrf_flops, ms_per, out)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, n, c)
+    print(json.dumps(out), flush=True)
+
+
+def measure_matrix_free(n3p, torch, dev, n, c, prec, solver, x, ws, out):
     opts_mf = n3p.Options.default(fft_residual=1, matrix_free=1)
     ws_mf = torch.empty(n3p.workspace_size(n, prec, solver, opts_mf), dtype=torch.uint8, device=dev)
     x.fill_(1.0)
@@ -199,40 +219,54 @@ def main():
                               "workspace_gib": ws_mf.numel() / 2 ** 30,
                               "workspace_gib_stored_J": ws.numel() / 2 ** 30}
     del ws_mf
-    if not args.no_fp64:
-        opts64 = n3p.Options.default()
-        ws64 = torch.empty(n3p.workspace_size(n, n3p.FP64, n3p.DIRECT, opts64), dtype=torch.uint8,
-                           device=dev)
-        x.fill_(1.0)
-        n3p.solve_heq(n, c, x=x, prec=n3p.FP64, solver=n3p.DIRECT, opts=opts64, ws=ws64)
+
+
+def fp64_baseline(n3p, torch, dev, n, c, x, getrf_flops, ms_per, out):
+    """FP64-LU Newton (the FP64 Jacobian factored in FP64, one solve per step)."""
+    opts64 = n3p.Options.default()
+    ws64 = torch.empty(n3p.workspace_size(n, n3p.FP64, n3p.DIRECT, opts64), dtype=torch.uint8,
+                       device=dev)
+    x.fill_(1.0)
+    n3p.solve_heq(n, c, x=x, prec=n3p.FP64, solver=n3p.DIRECT, opts=opts64, ws=ws64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x.fill_(1.0)
+    _, rep64 = n3p.solve_heq(n, c, x=x, prec=n3p.FP64, solver=n3p.DIRECT, opts=opts64, ws=ws64)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3
+    g64 = rep64.ms_getrf / max(rep64.its, 1)
+    out["fp64_lu_newton"] = {"ms": ms64, "its": rep64.its, "getrf_ms": g64,
+                             "getrf_tflops": getrf_flops / (g64 * 1e-3) / 1e12,
+                             "speedup_3p_vs_fp64": ms64 / ms_per}
+    del ws64
+    # vendor FP64 LU for context (rocSOLVER through torch), one factorisation
+    try:
+        A = torch.randn(n, n, dtype=torch.float64, device=dev) + n * torch.eye(
+            n, dtype=torch.float64, device=dev)
+        torch.linalg.lu_factor(A)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x.fill_(1.0)
-        _, rep64 = n3p.solve_heq(n, c, x=x, prec=n3p.FP64, solver=n3p.DIRECT, opts=opts64,
-                                 ws=ws64)
+        torch.linalg.lu_factor(A)
         torch.cuda.synchronize()
-        ms64 = (time.perf_counter() - t0) * 1e3
-        g64 = rep64.ms_getrf / max(rep64.its, 1)
-        out["fp64_lu_newton"] = {"ms": ms64, "its": rep64.its, "getrf_ms": g64,
-                                 "getrf_tflops": getrf_flops / (g64 * 1e-3) / 1e12,
-                                 "speedup_3p_vs_fp64": ms64 / ms_per}
-        del ws64
-        # vendor FP64 LU for context (rocSOLVER through torch), one factorisation
-        try:
-            A = torch.randn(n, n, dtype=torch.float64, device=dev) + n * torch.eye(
-                n, dtype=torch.float64, device=dev)
-            torch.linalg.lu_factor(A)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            torch.linalg.lu_factor(A)
-            torch.cuda.synchronize()
-            out["fp64_lu_newton"]["rocsolver_getrf_ms"] = (time.perf_counter() - t0) * 1e3
-            del A
-        except Exception as e:  # context only
-            out["fp64_lu_newton"]["rocsolver_getrf_ms"] = "unavailable: %s" % type(e).__name__
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, n, c)
-    print(json.dumps(out), flush=True)
+        out["fp64_lu_newton"]["rocsolver_getrf_ms"] = (time.perf_counter() - t0) * 1e3
+        del A
+    except Exception as e:  # context only
+        out["fp64_lu_newton"]["rocsolver_getrf_ms"] = "unavailable: %s" % type(e).__name__
+
+
+def measured_traffic(n, prec):
+    """HBM bytes per factorisation from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), only if
+    the factorisation kernels' source is unchanged since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "getrf_traffic_n%d_%s.json" % (n, prec.lower()))
+    src = os.path.join(ROOT, "paper_2307_16051_amd", "csrc", "k_getrf.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec.get("bytes_per_factorisation") if rec.get("k_getrf_sha256") == sha else None
 
 
 if __name__ == "__main__":
