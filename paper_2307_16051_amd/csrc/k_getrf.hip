@@ -499,6 +499,34 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
     gemm16_tile<T, TM, TN, WGM, WGN, KC>(tm * TM, tn * TN, K, At, ldat, B, ldb, C, ldc, flags);
 }
 
+// Two independent updates with the same K in one launch (tiles of the first,
+// then of the second): after a leaf, the rest of its panel (below) and the
+// row block right of the panel write disjoint parts of C and only read L and U.
+struct GemmProb {
+    int M, N;
+    const void *At;
+    int64_t ldat;
+    const void *B;
+    int64_t ldb;
+    void *C;
+    int64_t ldc;
+};
+
+template <typename T, int TM, int TN, int WGM, int WGN, int KC>
+__global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16_pair(GemmProb p1, GemmProb p2, int K,
+                                                               int *__restrict__ flags)
+{
+    if (block_flag(&flags[FLAG_FAIL])) return;
+    const int nt1 = (p1.M / TM) * (p1.N / TN);
+    int tile = blockIdx.x;
+    const GemmProb &p = tile < nt1 ? p1 : p2;
+    if (tile >= nt1) tile -= nt1;
+    const int ntm = p.M / TM;
+    const int tm = tile % ntm, tn = tile / ntm;
+    gemm16_tile<T, TM, TN, WGM, WGN, KC>(tm * TM, tn * TN, K, (const T *)p.At, p.ldat, (const T *)p.B,
+                                         p.ldb, (T *)p.C, p.ldc, flags);
+}
+
 // ========================================== Schur GEMM, FP32/FP64 matrix cores
 template <typename T> struct mfma16x4;
 // Output layout of the 16x16 fragment: lane l holds column l & 15; register q
@@ -942,6 +970,41 @@ hipError_t launch_gemm_sub(int prec, int64_t M, int64_t N, int64_t K, const void
     case N3P_FP64: return gemm4_t<double>(M, N, K, At, ldat, B, ldb, C, ldc, flags, check_abort, s);
     }
     return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t gemm16_pair_t(GemmProb a, GemmProb b, int K, int *flags, hipStream_t s)
+{
+    auto fits = [](const GemmProb &q, int t) { return q.M % t == 0 && q.N % t == 0; };
+    if (fits(a, 128) && fits(b, 128)) {
+        const unsigned g = (unsigned)((a.M / 128) * (a.N / 128) + (b.M / 128) * (b.N / 128));
+        hipLaunchKernelGGL((k_gemm16_pair<T, 128, 128, 2, 2, 32>), dim3(g), dim3(256), 0, s, a, b, K, flags);
+    } else {
+        const unsigned g = (unsigned)((a.M / 64) * (a.N / 64) + (b.M / 64) * (b.N / 64));
+        hipLaunchKernelGGL((k_gemm16_pair<T, 64, 64, 2, 2, 32>), dim3(g), dim3(256), 0, s, a, b, K, flags);
+    }
+    return hipGetLastError();
+}
+
+// C1 -= At1^T B1 and C2 -= At2^T B2 (same K) in one launch; FP16/BF16 only,
+// every M, N a multiple of 64 and K of 32.  An empty problem is allowed.
+hipError_t launch_gemm_pair(int prec, int64_t M1, int64_t N1, const void *At1, int64_t ldat1,
+                            const void *B1, int64_t ldb1, void *C1, int64_t ldc1, int64_t M2,
+                            int64_t N2, const void *At2, int64_t ldat2, const void *B2,
+                            int64_t ldb2, void *C2, int64_t ldc2, int64_t K, int *flags,
+                            hipStream_t s)
+{
+    if (M1 % 64 || N1 % 64 || M2 % 64 || N2 % 64 || K % 32 || K <= 0) return hipErrorInvalidValue;
+    GemmProb a{(int)M1, (int)N1, At1, ldat1, B1, ldb1, C1, ldc1};
+    GemmProb b{(int)M2, (int)N2, At2, ldat2, B2, ldb2, C2, ldc2};
+    if (M1 <= 0 || N1 <= 0) { a.M = 0; a.N = 64; }
+    if (M2 <= 0 || N2 <= 0) { b.M = 0; b.N = 64; }
+    if (a.M == 0 && b.M == 0) return hipSuccess;
+    switch (prec) {
+    case N3P_FP16: return gemm16_pair_t<f16>(a, b, (int)K, flags, s);
+    case N3P_BF16: return gemm16_pair_t<bf16>(a, b, (int)K, flags, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int R>

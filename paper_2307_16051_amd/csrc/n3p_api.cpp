@@ -137,13 +137,21 @@ int getrf_spec(const FactorWs &f, hipStream_t s)
             const int64_t c1 = c0 + NB_LEAF;
             if (c1 < kend) {
                 const void *At = LT + ((size_t)c1 * NB_OUT + (size_t)(c0 - k0)) * es;
-                // rest of the outer panel
-                HIPCHK(launch_gemm_sub(prec, Np - c1, kend - c1, NB_LEAF, At, NB_OUT, at(c0, c1),
-                                       lda, at(c1, c1), lda, f.flags, true, s));
-                // rest of the outer row block, right of the panel
-                if (kend < Np)
-                    HIPCHK(launch_gemm_sub(prec, kend - c1, Np - kend, NB_LEAF, At, NB_OUT,
-                                           at(c0, kend), lda, at(c1, kend), lda, f.flags, true, s));
+                if (prec == N3P_FP16 || prec == N3P_BF16) {
+                    // rest of the outer panel (below) and rest of the outer row
+                    // block (right of the panel): one launch
+                    HIPCHK(launch_gemm_pair(prec, Np - c1, kend - c1, At, NB_OUT, at(c0, c1), lda,
+                                            at(c1, c1), lda, kend - c1, Np - kend, At, NB_OUT,
+                                            at(c0, kend), lda, at(c1, kend), lda, NB_LEAF, f.flags,
+                                            s));
+                } else {
+                    HIPCHK(launch_gemm_sub(prec, Np - c1, kend - c1, NB_LEAF, At, NB_OUT,
+                                           at(c0, c1), lda, at(c1, c1), lda, f.flags, true, s));
+                    if (kend < Np)
+                        HIPCHK(launch_gemm_sub(prec, kend - c1, Np - kend, NB_LEAF, At, NB_OUT,
+                                               at(c0, kend), lda, at(c1, kend), lda, f.flags, true,
+                                               s));
+                }
             }
         }
         if (kend < Np) {

@@ -166,6 +166,11 @@ hipError_t launch_f64_to_f32(int64_t n, const double *src, float *dst, hipStream
 // factorisation kernels
 hipError_t launch_leaf_spec(int prec, int64_t Np, int64_t c0, void *A, int64_t lda, void *LT,
                             int64_t k0, int *flags, hipStream_t s);
+hipError_t launch_gemm_pair(int prec, int64_t M1, int64_t N1, const void *At1, int64_t ldat1,
+                            const void *B1, int64_t ldb1, void *C1, int64_t ldc1, int64_t M2,
+                            int64_t N2, const void *At2, int64_t ldat2, const void *B2,
+                            int64_t ldb2, void *C2, int64_t ldc2, int64_t K, int *flags,
+                            hipStream_t s);
 hipError_t launch_gemm_sub(int prec, int64_t M, int64_t N, int64_t K, const void *At,
                            int64_t ldat, const void *B, int64_t ldb, void *C, int64_t ldc,
                            int *flags, bool check_abort, hipStream_t s);
