@@ -3,7 +3,7 @@
 // The factorisation (Gaussian elimination, Section 1.3; the half-precision
 // factorisation J_h = L U of Section 2) runs on the padded Np x Np copy:
 //
-//   for each outer block of NB_OUT columns:
+//   for each outer block of NB_OUT columns (1024; sizes padded to 512):
 //     for each leaf of NB_LEAF columns inside it:
 //       leaf kernel   -- factor the leaf, form L21 and the U row block
 //       inner GEMMs   -- update the rest of the outer block (K = NB_LEAF)

@@ -61,7 +61,7 @@ struct Bump {
 };
 
 bool valid_prec(int p) { return p >= N3P_FP16 && p <= N3P_FP64; }
-int64_t padded(int64_t n) { return round_up(std::max<int64_t>(n, 1), NB_OUT); }
+int64_t padded(int64_t n) { return round_up(std::max<int64_t>(n, 1), NB_PAD); }
 
 // ------------------------------------------------------------ factor state
 struct FactorWs {

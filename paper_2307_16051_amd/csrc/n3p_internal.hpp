@@ -2,7 +2,7 @@
 //
 // Storage conventions (all kernels):
 //   * matrices are column-major; the factorisation works on an Np x Np copy
-//     with Np = n rounded up to a multiple of NB_OUT, padded with the
+//     with Np = n rounded up to a multiple of NB_PAD, padded with the
 //     identity (the padded LU is the LU of J plus an identity block);
 //   * "LT" is the L panel of the current outer block stored row-major
 //     (K-contiguous) so that both operands of the Schur-complement GEMM feed
@@ -21,7 +21,8 @@
 
 namespace n3p {
 
-constexpr int NB_OUT = 512;   // outer block: K of the big Schur-complement GEMM
+constexpr int NB_OUT = 1024;  // outer block: K of the big Schur-complement GEMM
+constexpr int NB_PAD = 512;   // factorisation sizes are padded to a multiple of this
 constexpr int NB_LEAF = 64;   // leaf panel width
 constexpr int TRSV_BS = 64;   // row block of the triangular solves
 constexpr int FLAG_FAIL = 0, FLAG_NONFINITE = 1, FLAG_ZEROPIV = 2, FLAG_TIMEOUT = 3;
