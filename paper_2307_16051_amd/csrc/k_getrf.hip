@@ -112,13 +112,28 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
     }
     if (t == 0) sfail = 0;
     constexpr int CH = 16 / (int)sizeof(T);  // elements per 16-byte chunk
-    union Chunk { uint4 v; T e[CH]; };
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    union Chunk { u32x4 v; T e[CH]; };
     for (int e = t; e < L * L / CH; e += NT) {  // diagonal block, column chunks
         const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
         Chunk ch;
-        ch.v = *(const uint4 *)(A + (c0 + i0) + (c0 + j) * lda);
+        ch.v = *(const u32x4 *)(A + (c0 + i0) + (c0 + j) * lda);
 #pragma unroll
         for (int u = 0; u < CH; ++u) Dm[i0 + u][j] = (CT)to_f32(ch.e[u]);
+    }
+    // this workgroup's tile (64 rows of L21 or 64 columns of U12), loaded now
+    // into registers so the loads overlap the diagonal factorisation
+    constexpr int NPRE = L * L / CH / NT;
+    const T *tsrc = nullptr;
+    if (bid < nrt) tsrc = A + (c0 + L + (int64_t)bid * L) + c0 * lda;
+    else if (bid - nrt < nct) tsrc = A + c0 + (c0 + L + (int64_t)(bid - nrt) * L) * lda;
+    u32x4 pre[NPRE];
+    if (tsrc) {
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+            const int e = t + k * NT, i0 = (e % (L / CH)) * CH, j = e / (L / CH);
+            pre[k] = *(const u32x4 *)(tsrc + i0 + j * lda);
+        }
     }
     __syncthreads();
     const CT margin = (CT)(1.0 - 1.0 / 256.0);
@@ -199,10 +214,11 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
         // partial pivoting would compare: it checks it against the pivot,
         // scales it and broadcasts it to its octet.
         const int64_t R0 = c0 + L + (int64_t)bid * L;
-        for (int e = t; e < L * L / CH; e += NT) {  // coalesced: column chunks
-            const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {  // the prefetched column chunks
+            const int e = t + k * NT, i0 = (e % (L / CH)) * CH, j = e / (L / CH);
             Chunk ch;
-            ch.v = *(const uint4 *)(A + (R0 + i0) + (c0 + j) * lda);
+            ch.v = pre[k];
 #pragma unroll
             for (int u = 0; u < CH; ++u) Sg[i0 + u][j] = (CT)to_f32(ch.e[u]);
         }
@@ -253,14 +269,14 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
                 bad |= !isfinite(Sg[i0 + u][j]);
                 ch.e[u] = to_store_d<T>((double)Sg[i0 + u][j]);
             }
-            *(uint4 *)(A + (R0 + i0) + (c0 + j) * lda) = ch.v;
+            *(u32x4 *)(A + (R0 + i0) + (c0 + j) * lda) = ch.v;
         }
         for (int e = t; e < L * L / CH; e += NT) {  // LT: row chunks (K contiguous)
             const int i = e / (L / CH), j0 = (e % (L / CH)) * CH;
             Chunk ch;
 #pragma unroll
             for (int u = 0; u < CH; ++u) ch.e[u] = to_store_d<T>((double)Sg[i][j0 + u]);
-            *(uint4 *)(LT + (R0 + i) * ldlt + ltcol + j0) = ch.v;
+            *(u32x4 *)(LT + (R0 + i) * ldlt + ltcol + j0) = ch.v;
         }
         if (fail) set_flag(&flags[FLAG_FAIL], 1);
     } else if (bid - nrt < nct) {
@@ -268,10 +284,11 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
         // lower L11.  Octet w8 owns column C0 + w8; lane g holds rows
         // 8(u + ku) + g of the current group ku.
         const int64_t C0 = c0 + L + (int64_t)(bid - nrt) * L;
-        for (int e = t; e < L * L / CH; e += NT) {
-            const int i0 = (e % (L / CH)) * CH, j = e / (L / CH);
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {  // the prefetched column chunks
+            const int e = t + k * NT, i0 = (e % (L / CH)) * CH, j = e / (L / CH);
             Chunk ch;
-            ch.v = *(const uint4 *)(A + (c0 + i0) + (C0 + j) * lda);
+            ch.v = pre[k];
 #pragma unroll
             for (int u = 0; u < CH; ++u) Sg[i0 + u][j] = (CT)to_f32(ch.e[u]);
         }
@@ -315,7 +332,7 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
                 bad |= !isfinite(Sg[i0 + u][j]);
                 ch.e[u] = to_store_d<T>((double)Sg[i0 + u][j]);
             }
-            *(uint4 *)(A + (c0 + i0) + (C0 + j) * lda) = ch.v;
+            *(u32x4 *)(A + (c0 + i0) + (C0 + j) * lda) = ch.v;
         }
     }
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
