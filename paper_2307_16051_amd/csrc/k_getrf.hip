@@ -266,8 +266,8 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
             Chunk ch;
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
-                bad |= !isfinite(Sg[i0 + u][j]);
                 ch.e[u] = to_store_d<T>((double)Sg[i0 + u][j]);
+                bad |= !isfinite(to_f32(ch.e[u]));  // the stored value
             }
             *(u32x4 *)(A + (R0 + i0) + (c0 + j) * lda) = ch.v;
         }
@@ -329,8 +329,8 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
             Chunk ch;
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
-                bad |= !isfinite(Sg[i0 + u][j]);
                 ch.e[u] = to_store_d<T>((double)Sg[i0 + u][j]);
+                bad |= !isfinite(to_f32(ch.e[u]));  // the stored value
             }
             *(u32x4 *)(A + (c0 + i0) + (C0 + j) * lda) = ch.v;
         }
@@ -825,7 +825,7 @@ __global__ __launch_bounds__(PP_THREADS) void k_pivot_panel(int64_t Np, int64_t 
     for (int64_t e = tid; e < m * L; e += PP_THREADS) {
         const int64_t i = e % m, j = e / m;
         const T v = to_store_d<T>((double)S[e]);
-        if (!isfinite(S[e])) bad = true;
+        if (!isfinite(to_f32(v))) bad = true;  // the stored value (FP16 overflows above 65504)
         A[(c0 + i) + (c0 + j) * lda] = v;
         if (i >= L) LT[(c0 + i) * (int64_t)NB_OUT + (c0 - k0) + j] = v;
     }
@@ -881,8 +881,9 @@ __global__ __launch_bounds__(256) void k_u12(int64_t Np, int64_t c0, T *__restri
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        if (!isfinite(y[k])) bad = true;
-        col[k] = to_store_d<T>((double)y[k]);
+        const T v = to_store_d<T>((double)y[k]);
+        if (!isfinite(to_f32(v))) bad = true;
+        col[k] = v;
     }
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
 }

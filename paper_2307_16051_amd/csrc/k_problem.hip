@@ -151,11 +151,15 @@ __device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np,
         const double di = D[i];
         const double kij = wgt * ((double)i + 0.5) * (h ? h[i + j] : 1.0 / (double)(i + j + 1));
         const double v = (i == j ? 1.0 : 0.0) - kij / (di * di);
-        if constexpr (std::is_same<T, double>::value)
+        if constexpr (std::is_same<T, double>::value) {
             col[i] = v;  // a double-precision factorisation takes the FP64 Jacobian itself
-        else
-            col[i] = cvt_out<T>((float)v * s);
+        } else {
+            const T o = cvt_out<T>((float)v * s);
+            if (!isfinite((float)o)) bad = true;  // the stored value (FP16 range)
+            col[i] = o;
+        }
     }
+    if (bad && flags) set_flag(&flags[FLAG_NONFINITE], 1);
     for (int64_t i = n + t; i < Np; i += 256) col[i] = cvt_out<T>(0.0f);
 }
 
@@ -202,7 +206,13 @@ __global__ __launch_bounds__(256) void k_round_scale(int64_t n, int64_t Np, cons
         s = col_scale_from_max(block_max_256(mx, sh), target_log2);
         if (t == 0) colscale[j] = s;
     }
-    for (int64_t i = t; i < n; i += 256) col[i] = cvt_out<T>(src[i] * s);
+    bool over = false;
+    for (int64_t i = t; i < n; i += 256) {
+        const T o = cvt_out<T>(src[i] * s);
+        over |= !isfinite((double)o);  // the stored value (FP16 range)
+        col[i] = o;
+    }
+    if (over && flags) set_flag(&flags[FLAG_NONFINITE], 1);
     for (int64_t i = n + t; i < Np; i += 256) col[i] = cvt_out<T>(0.0f);
 }
 
