@@ -83,9 +83,10 @@ typedef enum n3p_linsolver { N3P_IR = 0, N3P_GMRES_IR = 1, N3P_DIRECT = 2 } n3p_
 
 /* Half-precision range handling (Section 1.2 warns about the range of half
  * precision; eqs. (2.17)-(2.18) scale the right-hand side).
- *   N3P_SCALE_AUTO  FP16: power-of-two column scaling of the half copy,
- *                   retried once with a smaller target on overflow; other
- *                   precisions: no scaling
+ *   N3P_SCALE_AUTO  FP16: power-of-two column scaling of the half copy; on
+ *                   overflow the factorisation is redone once with targets
+ *                   2^6 smaller, which are then kept for the rest of the
+ *                   solve; other precisions: no scaling
  *   N3P_SCALE_NONE  plain rounding I_s^h(J) */
 typedef enum n3p_scale { N3P_SCALE_AUTO = 0, N3P_SCALE_NONE = 1 } n3p_scale;
 

@@ -70,7 +70,7 @@ struct FactorWs {
     void *A = nullptr;        // Np x Np, ld Np
     void *LT = nullptr;       // Np x NB_OUT
     void *DG = nullptr;       // 2 x NB_LEAF^2
-    void *scratch = nullptr;  // Np x NB_LEAF compute type
+    void *xch = nullptr;      // pivoting path: exchange words and interchange list
     int32_t *ipiv = nullptr;  // Np
     int32_t *perm = nullptr;  // Np (device), valid if pivoted
     int *flags = nullptr;     // NFLAGS
@@ -79,11 +79,10 @@ struct FactorWs {
 size_t factor_bytes(int prec, int64_t Np, Bump &b, FactorWs *f, char *base)
 {
     const size_t es = elem_size(prec);
-    const size_t cs = prec == N3P_FP64 ? 8 : 4;
     size_t oA = b.take((size_t)Np * Np * es);
     size_t oLT = b.take((size_t)Np * NB_OUT * es);
     size_t oDG = b.take((size_t)2 * NB_LEAF * NB_LEAF * es);
-    size_t oS = b.take((size_t)Np * NB_LEAF * cs);
+    size_t oS = b.take(pivot_xch_bytes(prec, Np));
     size_t oI = b.take((size_t)Np * 4);
     size_t oP = b.take((size_t)Np * 4);
     size_t oF = b.take((size_t)NFLAGS * 4);
@@ -93,7 +92,7 @@ size_t factor_bytes(int prec, int64_t Np, Bump &b, FactorWs *f, char *base)
         f->A = base + oA;
         f->LT = base + oLT;
         f->DG = base + oDG;
-        f->scratch = base + oS;
+        f->xch = base + oS;
         f->ipiv = (int32_t *)(base + oI);
         f->perm = (int32_t *)(base + oP);
         f->flags = (int *)(base + oF);
@@ -165,7 +164,15 @@ int getrf_spec(const FactorWs &f, hipStream_t s)
     return 0;
 }
 
-// Explicit partial pivoting, one 64-column panel at a time.
+// Explicit partial pivoting, blocked like getrf_spec, except that rows to
+// the right of an outer block are touched only once the whole block is
+// pivoted (a later leaf may interchange a row of the block with one below it).
+// Per leaf: the cooperative panel (pivot search, interchanges inside the leaf,
+// L21, ipiv), the leaf's interchanges on every other column, and the U row
+// block and rank-64 update inside the outer block.  Per outer block: LT
+// rebuilt after all of its interchanges, the U row block right of it (leaf by
+// leaf: triangular solve, then rank-64 update of the block's later rows), and
+// the K = NB_OUT update of the trailing matrix.
 int getrf_pivot(const FactorWs &f, hipStream_t s)
 {
     const int prec = f.prec;
@@ -174,17 +181,32 @@ int getrf_pivot(const FactorWs &f, hipStream_t s)
     char *A = (char *)f.A;
     char *LT = (char *)f.LT;
     auto at = [&](int64_t i, int64_t j) { return (void *)(A + ((size_t)i + (size_t)j * lda) * es); };
-    for (int64_t c0 = 0; c0 < Np; c0 += NB_LEAF) {
-        HIPCHK(launch_pivot_panel(prec, Np, c0, f.A, lda, f.ipiv, f.LT, c0, (float *)f.scratch,
-                                  f.flags, s));
-        const int64_t c1 = c0 + NB_LEAF;
-        HIPCHK(launch_laswp(prec, Np, f.A, lda, f.ipiv, c0, c1, 0, c0, s));
-        HIPCHK(launch_laswp(prec, Np, f.A, lda, f.ipiv, c0, c1, c1, Np, s));
-        if (c1 < Np) {
-            HIPCHK(launch_u12(prec, Np, c0, f.A, lda, f.flags, s));
-            const void *At = LT + (size_t)c1 * NB_OUT * es;
-            HIPCHK(launch_gemm_sub(prec, Np - c1, Np - c1, NB_LEAF, At, NB_OUT, at(c0, c1), lda,
-                                   at(c1, c1), lda, f.flags, false, s));
+    auto lt = [&](int64_t row, int64_t col) { return (const void *)(LT + ((size_t)row * NB_OUT + (size_t)col) * es); };
+    HIPCHK(launch_pivot_reset(prec, Np, f.xch, s));
+    for (int64_t k0 = 0; k0 < Np; k0 += NB_OUT) {
+        const int64_t kend = std::min<int64_t>(k0 + NB_OUT, Np);
+        for (int64_t c0 = k0; c0 < kend; c0 += NB_LEAF) {
+            HIPCHK(launch_pivot_coop(prec, Np, c0, k0, f.A, lda, f.ipiv, f.LT, f.xch, f.flags, s));
+            HIPCHK(launch_row_gather(prec, Np, c0, f.A, lda, f.xch, s));
+            const int64_t c1 = c0 + NB_LEAF;
+            if (c1 < kend) {
+                HIPCHK(launch_u12(prec, c0, c1, kend, f.A, lda, f.flags, s));
+                HIPCHK(launch_gemm_sub(prec, Np - c1, kend - c1, NB_LEAF, lt(c1, c0 - k0), NB_OUT,
+                                       at(c0, c1), lda, at(c1, c1), lda, f.flags, false, s));
+            }
+        }
+        if (kend < Np) {
+            HIPCHK(launch_lt_rebuild(prec, Np, k0, k0, kend - k0, f.A, lda, f.LT, s));
+            for (int64_t c0 = k0; c0 < kend; c0 += NB_LEAF) {
+                const int64_t c1 = c0 + NB_LEAF;
+                HIPCHK(launch_u12(prec, c0, kend, Np, f.A, lda, f.flags, s));
+                if (c1 < kend)
+                    HIPCHK(launch_gemm_sub(prec, kend - c1, Np - kend, NB_LEAF, lt(c1, c0 - k0),
+                                           NB_OUT, at(c0, kend), lda, at(c1, kend), lda, f.flags,
+                                           false, s));
+            }
+            HIPCHK(launch_gemm_sub(prec, Np - kend, Np - kend, kend - k0, lt(kend, 0), NB_OUT,
+                                   at(k0, kend), lda, at(kend, kend), lda, f.flags, false, s));
         }
     }
     return 0;
@@ -790,9 +812,13 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
         lc.L = w.L;
     }
 
+    // FP16 column targets: column max in [256, 512), 2^7 headroom below 65504.
+    // A factorisation that overflows is redone with targets 2^6 lower, and the
+    // lower targets are kept for the rest of the solve (the Jacobian changes
+    // little from one Newton step to the next, so its growth does too).
+    float tl = 9.0f;
     while (fn > tau && its < opt.maxit) {
         // --- J = F'(x) stored FP32, J_h = I_s^h(J) (column scaled for FP16)
-        float tl = 9.0f;  // FP16: column max in [256, 512): 2^7 headroom below 65504
         bool scaled = want_scale;
         FactorResult fr;
         for (int attempt = 0; attempt < 2; ++attempt) {
@@ -812,7 +838,7 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
             CHK(getrf_run(w.f, s, refill, &fr));
             CHK(tstop(&t_getrf));
             if (fr.timeout) return N3P_E_TIMEOUT;
-            if (fr.nonfinite && want_scale && attempt == 0) {
+            if (fr.nonfinite && want_scale && attempt == 0 && tl > 3.0f) {
                 tl -= 6.0f;  // retry with the column targets 2^6 lower
                 continue;
             }

@@ -82,9 +82,12 @@ def test_getrf_fp64_no_interchange_path(env, n):
     np.testing.assert_allclose(from_cm(T), LU_ref, rtol=1e-11, atol=1e-13)
 
 
-@pytest.mark.parametrize("n", [64, 100, 513, 1024])
+@pytest.mark.parametrize("n", [64, 100, 513, 1024, 2500, 4100])
 def test_getrf_fp64_pivoting_path(env, n):
-    """Gaussian matrix: explicit partial pivoting; pivots equal the oracle's."""
+    """Gaussian matrix: explicit partial pivoting; pivots equal the oracle's.
+    Sizes above 1024 span several outer blocks of 1024 columns (the last one
+    partial), so interchanges reach rows below a block before its U row block
+    is formed."""
     n3p, torch = env
     print("case getrf_fp64_pivot n=%d" % n, flush=True)
     A = random_matrix(n, 100 + n)
@@ -119,7 +122,7 @@ def check_backward_error(A_in, LU, ipiv, u, nstages, u_acc, eta_sub):
 
 @pytest.mark.parametrize("prec,u", [("fp16", U16), ("bf16", UBF), ("fp32", U32)])
 @pytest.mark.parametrize("kind", ["dominant", "gaussian", "heq"])
-@pytest.mark.parametrize("n", [200, 1024])
+@pytest.mark.parametrize("n", [200, 1024, 2500])
 def test_getrf_low_precision_backward_error(env, prec, u, kind, n):
     n3p, torch = env
     print("case getrf_%s_%s n=%d" % (prec, kind, n), flush=True)
@@ -142,15 +145,42 @@ def test_getrf_low_precision_backward_error(env, prec, u, kind, n):
     check_backward_error(A_in, from_cm(T), piv, u, stages, U32, eta_sub)
 
 
-def test_getrf_singular_reports_info(env):
+@pytest.mark.parametrize("n,zc", [(130, 5), (1500, 1200)])
+def test_getrf_singular_reports_info(env, n, zc):
     n3p, torch = env
-    n = 130
     A = random_matrix(n, 3)
-    A[:, 5] = 0.0
+    A[:, zc] = 0.0
     T = to_cm(torch, A, torch.float64)
     ipiv, info = n3p.getrf(T)
-    _, _, info_ref = O.getrf(A)
-    assert info == info_ref == 6
+    _, piv_ref, info_ref = O.getrf(A)
+    assert info == info_ref == zc + 1
+    assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
+
+
+def test_getrf_fp64_pivoting_large_properties(env):
+    """N = 16500 (more than 64 panel workgroups): partial pivoting's
+    |L| <= 1 and the backward error of P A = L U, checked on the GPU.  The
+    oracle's factorisation at this size takes minutes, so the check is the
+    defining property: ||P A - L U||_max <= c n u ||L|| ||U|| (Wilkinson)."""
+    n3p, torch = env
+    n = 16500
+    print("case getrf_fp64_pivot_large n=%d" % n, flush=True)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    T = A.t().contiguous().t()          # column-major copy
+    ipiv, info = n3p.getrf(T)
+    assert info == 0
+    piv = ipiv.cpu().numpy()
+    assert np.all(piv >= np.arange(n)) and np.all(piv < n)
+    p = torch.from_numpy(O.perm_from_ipiv(piv)).cuda()
+    Lm = torch.tril(T, -1)
+    assert Lm.abs().max().item() <= 1.0
+    Lm.diagonal().fill_(1.0)
+    Um = torch.triu(T)
+    R = (A[p] - Lm @ Um).abs().max().item()
+    bound = 4 * n * 2.0 ** -53 * Lm.abs().max().item() * Um.abs().max().item() * n
+    print("  max|PA-LU| = %.3e (bound %.3e)" % (R, bound), flush=True)
+    assert R <= bound
 
 
 def test_getrf_tie_break_lowest_row(env):
