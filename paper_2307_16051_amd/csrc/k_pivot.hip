@@ -4,10 +4,12 @@
 // attempt of k_getrf.hip finds that partial pivoting would interchange rows.
 //
 // Per 64-column leaf: k_pivot_coop (pivot search, interchanges inside the
-// leaf, multipliers, ipiv), k_row_gather (the leaf's interchanges on every
-// other column), k_u12 (U row block); the Schur-complement updates reuse the
-// matrix-core GEMMs of k_getrf.hip, and k_lt_rebuild refreshes the transposed
-// L panel of an outer block once all of its interchanges are known.
+// leaf, multipliers, ipiv) and k_gather_u12 (the leaf's interchanges on the
+// rest of its outer block, and its U row block there).  Per outer block:
+// k_gather_block (the block's interchanges on all other columns),
+// k_lt_rebuild (the block's L transposed), k_u12 (U row blocks right of the
+// block).  The Schur-complement updates reuse the matrix-core GEMMs of
+// k_getrf.hip.
 #include <algorithm>
 
 #include "n3p_internal.hpp"
@@ -38,7 +40,9 @@ namespace n3p {
 // slots after each group, so the current group's columns always sit in slots
 // 0..7 (compile-time register indices): in group g, slot s holds panel column
 // (s + 8 g) mod 64 and slots >= 64 - 8 g hold finished columns.
-constexpr int PC_SPIN_LIMIT = 1 << 20;  // polls of ~1 us: a wait that long has failed
+constexpr int PC_SPIN_LIMIT = 1 << 20;
+constexpr int PC_LIST_INTS = 1 + 4 * NB_LEAF;  // count + 128 (dest, src) pairs
+constexpr int PC_NLIST = NB_OUT / NB_LEAF;     // one list per leaf of an outer block  // polls of ~1 us: a wait that long has failed
 
 template <typename CT> struct pc_cfg;
 // rows per thread, words per value, threads per workgroup
@@ -113,8 +117,9 @@ template <> struct vec16<double> { typedef double type __attribute__((ext_vector
 //   rows [2][pmax][64W]: the candidate rows, in register-slot order (every
 //                        workgroup is in the same column group when it reads)
 //   rowk [2][64W]      : row k before the interchange, slot order
-//   then int list[1 + 2*128]: count, (dest, src) row pairs of the leaf's
-//   interchanges composed into one permutation.
+//   then int list[16][PC_LIST_INTS]: per leaf of the outer block, the count
+//   and the (dest, src) row pairs of its interchanges composed into one
+//   permutation.
 // State of one thread of the panel kernel; step<KK>(g) is column 8 g + KK.
 template <typename T, typename CT>
 struct PcState {
@@ -348,7 +353,7 @@ __global__ __launch_bounds__(pc_cfg<CT>::TH) void k_pivot_coop(int64_t Np, int64
     st.pivs = pivs;
     st.dead = false;
     st.nonfin = false;
-    int *list = (int *)(st.rowk + 2 * L * W);
+    int *list = (int *)(st.rowk + 2 * L * W) + ((c0 - k0) / L) * PC_LIST_INTS;
     const int tid = st.tid, lane = st.lane, wv = st.wv, wg = st.wg, m = st.m;
 
 #pragma unroll
@@ -448,24 +453,105 @@ __global__ __launch_bounds__(pc_cfg<CT>::TH) void k_pivot_coop(int64_t Np, int64
     }
 }
 
-// A leaf's interchanges on every column outside the leaf: new[dest] = old[src]
-// for the listed (dest, src) pairs (at most 128).  Two columns per 256-thread
-// workgroup, one pair per thread; every read completes before any write.
+// Interchanges of an outer block's leaves (lists 0 .. nl-1, applied in order)
+// on the columns outside the block, [0, k0) and [kend, Np).  Two columns per
+// 256-thread workgroup, one row move per thread; every read of a list
+// completes before any write.
 template <typename T>
-__global__ __launch_bounds__(256) void k_row_gather(T *__restrict__ A, int64_t lda,
-                                                    const int *__restrict__ list, int64_t c0,
-                                                    int64_t ncol)
+__global__ __launch_bounds__(256) void k_gather_block(T *__restrict__ A, int64_t lda,
+                                                      const int *__restrict__ lists, int nl,
+                                                      int64_t k0, int64_t kend, int64_t ncol)
 {
     const int64_t q = (int64_t)blockIdx.x * 2 + (threadIdx.x >> 7);
     const int e = threadIdx.x & 127;
+    const bool colok = q < ncol;
+    T *cp = A + (q < k0 ? q : q - k0 + kend) * lda;
+    for (int l = 0; l < nl; ++l) {
+        const int *list = lists + l * PC_LIST_INTS;
+        const bool act = colok && e < list[0];
+        T x = (T)0.0f;
+        if (act) x = cp[list[2 + 2 * e]];
+        __syncthreads();
+        if (act) cp[list[1 + 2 * e]] = x;
+        __syncthreads();
+    }
+}
+
+// Forward substitution of one column's 64 rows [c0, c0 + 64) with the unit
+// lower L11 (in LDS): lane = row, the solved entries broadcast by readlane.
+template <typename T, typename CT>
+__device__ __forceinline__ void u12_column(T *__restrict__ cp, const CT (*Lm)[NB_LEAF + 1], int lane,
+                                           int *__restrict__ flags)
+{
+    constexpr int L = NB_LEAF;
+    CT lrow[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) lrow[k] = Lm[lane][k];
+    CT y = (CT)to_f32(cp[lane]);
+#pragma unroll
+    for (int k = 0; k < L - 1; ++k) {
+        const CT yk = lane_bcast(y, k);
+        if (lane > k) y -= lrow[k] * yk;
+    }
+    const T v = to_store_d<T>((double)y);
+    if (!isfinite(to_f32(v))) set_flag(&flags[FLAG_NONFINITE], 1);  // the stored value
+    cp[lane] = v;
+}
+
+template <typename T, typename CT>
+__device__ __forceinline__ void load_l11(const T *__restrict__ A, int64_t lda, int64_t c0,
+                                         CT (*Lm)[NB_LEAF + 1])
+{
+    for (int i = threadIdx.x; i < NB_LEAF * NB_LEAF; i += blockDim.x) {
+        const int r = i % NB_LEAF, j = i / NB_LEAF;
+        Lm[r][j] = (CT)to_f32(A[(c0 + r) + (c0 + j) * lda]);
+    }
+}
+
+// The leaf's interchanges on the other columns of its outer block [k0, kend),
+// and the leaf's U row block there: columns right of the leaf get the
+// interchanges and then the substitution with the leaf's L11; columns left
+// of it only the interchanges.  Four columns per 256-thread workgroup: the
+// row moves of all four first (every read before any write), then one
+// wavefront per column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_u12(T *__restrict__ A, int64_t lda,
+                                                    const int *__restrict__ list, int64_t c0,
+                                                    int64_t k0, int64_t kend,
+                                                    int *__restrict__ flags)
+{
+    typedef typename compute_of<T>::type CT;
+    constexpr int L = NB_LEAF;
+    __shared__ CT Lm[L][L + 1];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t ncol = kend - k0 - L, left = c0 - k0;
+    const int64_t q0 = (int64_t)blockIdx.x * 4;
     const int n = list[0];
-    const bool act = q < ncol && e < n;
-    const int64_t col = q < c0 ? q : q + NB_LEAF;
-    T *cp = A + col * lda;
-    T x = (T)0.0f;
-    if (act) x = cp[list[2 + 2 * e]];
+    T x[2];
+    bool act[2];
+    T *cp[2];
+    int dst[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int item = t + 256 * h, e = item & 127;
+        const int64_t q = q0 + (item >> 7);
+        act[h] = q < ncol && e < n;
+        cp[h] = A + (q < left ? k0 + q : k0 + q + L) * lda;
+        x[h] = (T)0.0f;
+        dst[h] = 0;
+        if (act[h]) {
+            x[h] = cp[h][list[2 + 2 * e]];
+            dst[h] = list[1 + 2 * e];
+        }
+    }
+    load_l11<T, CT>(A, lda, c0, Lm);
     __syncthreads();
-    if (act) cp[list[1 + 2 * e]] = x;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (act[h]) cp[h][dst[h]] = x[h];
+    __syncthreads();
+    const int64_t q = q0 + wv;
+    if (q < ncol && q >= left) u12_column<T, CT>(A + (k0 + q + L) * lda + c0, Lm, lane, flags);
 }
 
 // LT rows [r0, Np) for the outer block starting at column k0: the block's L
@@ -493,42 +579,18 @@ __global__ __launch_bounds__(256) void k_lt_rebuild(const T *__restrict__ A, int
 }
 
 // U row block of a factored leaf: rows [c0, c0+64) x columns [col0, col1),
-// forward substitution with the unit lower L11 taken from A.
+// with the unit lower L11 taken from A; one wavefront per column.
 template <typename T>
 __global__ __launch_bounds__(256) void k_u12(int64_t col0, int64_t col1, int64_t c0,
                                              T *__restrict__ A, int64_t lda,
                                              int *__restrict__ flags)
 {
     typedef typename compute_of<T>::type CT;
-    constexpr int L = NB_LEAF;
-    __shared__ CT Dm[L][L + 1];
-    const int t = threadIdx.x;
-    for (int e = t; e < L * L; e += 256) {
-        const int i = e % L, j = e / L;
-        Dm[i][j] = (CT)to_f32(A[(c0 + i) + (c0 + j) * lda]);
-    }
+    __shared__ CT Lm[NB_LEAF][NB_LEAF + 1];
+    load_l11<T, CT>(A, lda, c0, Lm);
     __syncthreads();
-    const int64_t jc = col0 + (int64_t)blockIdx.x * 256 + t;
-    if (jc >= col1) return;
-    T *col = A + jc * lda + c0;
-    CT y[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) y[k] = (CT)to_f32(col[k]);
-#pragma unroll
-    for (int k = 1; k < L; ++k) {
-        CT s = y[k];
-#pragma unroll
-        for (int m = 0; m < k; ++m) s -= Dm[k][m] * y[m];
-        y[k] = s;
-    }
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const T v = to_store_d<T>((double)y[k]);
-        if (!isfinite(to_f32(v))) bad = true;
-        col[k] = v;
-    }
-    if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
+    const int64_t jc = col0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (jc < col1) u12_column<T, CT>(A + jc * lda + c0, Lm, threadIdx.x & 63, flags);
 }
 
 // ================================================================ launchers
@@ -543,11 +605,20 @@ static int64_t pc_pmax(int prec, int64_t Np)
     return (Np + pc_rows_per_wg(prec) - 1) / pc_rows_per_wg(prec);
 }
 
-size_t pivot_xch_bytes(int prec, int64_t Np)
+static int64_t pc_words(int prec, int64_t Np)
 {
     const int64_t pmax = pc_pmax(prec, Np), W = prec == N3P_FP64 ? 2 : 1;
-    const int64_t words = 8 * pmax + 2 * pmax * NB_LEAF * W + 2 * NB_LEAF * W;
-    return (size_t)words * 8 + (size_t)(1 + 4 * NB_LEAF) * 4;
+    return 8 * pmax + 2 * pmax * NB_LEAF * W + 2 * NB_LEAF * W;
+}
+
+size_t pivot_xch_bytes(int prec, int64_t Np)
+{
+    return (size_t)pc_words(prec, Np) * 8 + (size_t)PC_NLIST * PC_LIST_INTS * 4;
+}
+
+static const int *pc_lists(int prec, int64_t Np, const void *xch)
+{
+    return (const int *)((const uint64_t *)xch + pc_words(prec, Np));
 }
 
 hipError_t launch_pivot_reset(int prec, int64_t Np, void *xch, hipStream_t s)
@@ -580,20 +651,36 @@ hipError_t launch_pivot_coop(int prec, int64_t Np, int64_t c0, int64_t k0, void 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_row_gather(int prec, int64_t Np, int64_t c0, void *A, int64_t lda,
-                             const void *xch, hipStream_t s)
+hipError_t launch_gather_u12(int prec, int64_t Np, int64_t c0, int64_t k0, int64_t kend, void *A,
+                             int64_t lda, const void *xch, int *flags, hipStream_t s)
 {
-    const int64_t pmax = pc_pmax(prec, Np), W = prec == N3P_FP64 ? 2 : 1;
-    const int *list = (const int *)((const uint64_t *)xch + 8 * pmax + 2 * pmax * NB_LEAF * W +
-                                    2 * NB_LEAF * W);
-    const int64_t ncol = Np - NB_LEAF;
+    const int64_t ncol = kend - k0 - NB_LEAF;
     if (ncol <= 0) return hipSuccess;
+    const int *list = pc_lists(prec, Np, xch) + ((c0 - k0) / NB_LEAF) * PC_LIST_INTS;
+    const unsigned grid = (unsigned)((ncol + 3) / 4);
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_gather_u12<f16>, dim3(grid), dim3(256), 0, s, (f16 *)A, lda, list, c0, k0, kend, flags); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_gather_u12<bf16>, dim3(grid), dim3(256), 0, s, (bf16 *)A, lda, list, c0, k0, kend, flags); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_gather_u12<float>, dim3(grid), dim3(256), 0, s, (float *)A, lda, list, c0, k0, kend, flags); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_gather_u12<double>, dim3(grid), dim3(256), 0, s, (double *)A, lda, list, c0, k0, kend, flags); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_block(int prec, int64_t Np, int64_t k0, int64_t kend, void *A,
+                               int64_t lda, const void *xch, hipStream_t s)
+{
+    const int64_t ncol = k0 + (Np - kend);
+    const int nl = (int)((kend - k0) / NB_LEAF);
+    if (ncol <= 0 || nl <= 0 || nl > PC_NLIST) return nl > PC_NLIST ? hipErrorInvalidValue : hipSuccess;
+    const int *lists = pc_lists(prec, Np, xch);
     const unsigned grid = (unsigned)((ncol + 1) / 2);
     switch (prec) {
-    case N3P_FP16: hipLaunchKernelGGL(k_row_gather<f16>, dim3(grid), dim3(256), 0, s, (f16 *)A, lda, list, c0, ncol); break;
-    case N3P_BF16: hipLaunchKernelGGL(k_row_gather<bf16>, dim3(grid), dim3(256), 0, s, (bf16 *)A, lda, list, c0, ncol); break;
-    case N3P_FP32: hipLaunchKernelGGL(k_row_gather<float>, dim3(grid), dim3(256), 0, s, (float *)A, lda, list, c0, ncol); break;
-    case N3P_FP64: hipLaunchKernelGGL(k_row_gather<double>, dim3(grid), dim3(256), 0, s, (double *)A, lda, list, c0, ncol); break;
+    case N3P_FP16: hipLaunchKernelGGL(k_gather_block<f16>, dim3(grid), dim3(256), 0, s, (f16 *)A, lda, lists, nl, k0, kend, ncol); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_gather_block<bf16>, dim3(grid), dim3(256), 0, s, (bf16 *)A, lda, lists, nl, k0, kend, ncol); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_gather_block<float>, dim3(grid), dim3(256), 0, s, (float *)A, lda, lists, nl, k0, kend, ncol); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_gather_block<double>, dim3(grid), dim3(256), 0, s, (double *)A, lda, lists, nl, k0, kend, ncol); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -620,7 +707,7 @@ hipError_t launch_u12(int prec, int64_t c0, int64_t col0, int64_t col1, void *A,
 {
     const int64_t ncol = col1 - col0;
     if (ncol <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((ncol + 255) / 256);
+    const unsigned grid = (unsigned)((ncol + 3) / 4);
     switch (prec) {
     case N3P_FP16: hipLaunchKernelGGL(k_u12<f16>, dim3(grid), dim3(256), 0, s, col0, col1, c0, (f16 *)A, lda, flags); break;
     case N3P_BF16: hipLaunchKernelGGL(k_u12<bf16>, dim3(grid), dim3(256), 0, s, col0, col1, c0, (bf16 *)A, lda, flags); break;

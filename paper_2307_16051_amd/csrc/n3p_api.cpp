@@ -168,11 +168,12 @@ int getrf_spec(const FactorWs &f, hipStream_t s)
 // the right of an outer block are touched only once the whole block is
 // pivoted (a later leaf may interchange a row of the block with one below it).
 // Per leaf: the cooperative panel (pivot search, interchanges inside the leaf,
-// L21, ipiv), the leaf's interchanges on every other column, and the U row
-// block and rank-64 update inside the outer block.  Per outer block: LT
-// rebuilt after all of its interchanges, the U row block right of it (leaf by
-// leaf: triangular solve, then rank-64 update of the block's later rows), and
-// the K = NB_OUT update of the trailing matrix.
+// L21, ipiv), the leaf's interchanges on the rest of the outer block with its
+// U row block there, and the rank-64 update inside the block.  Per outer
+// block: the block's interchanges on every other column, LT rebuilt, the U
+// row block right of the block (leaf by leaf: triangular solve, then rank-64
+// update of the block's later rows), and the K = NB_OUT update of the
+// trailing matrix.
 int getrf_pivot(const FactorWs &f, hipStream_t s)
 {
     const int prec = f.prec;
@@ -187,14 +188,14 @@ int getrf_pivot(const FactorWs &f, hipStream_t s)
         const int64_t kend = std::min<int64_t>(k0 + NB_OUT, Np);
         for (int64_t c0 = k0; c0 < kend; c0 += NB_LEAF) {
             HIPCHK(launch_pivot_coop(prec, Np, c0, k0, f.A, lda, f.ipiv, f.LT, f.xch, f.flags, s));
-            HIPCHK(launch_row_gather(prec, Np, c0, f.A, lda, f.xch, s));
+            HIPCHK(launch_gather_u12(prec, Np, c0, k0, kend, f.A, lda, f.xch, f.flags, s));
             const int64_t c1 = c0 + NB_LEAF;
             if (c1 < kend) {
-                HIPCHK(launch_u12(prec, c0, c1, kend, f.A, lda, f.flags, s));
                 HIPCHK(launch_gemm_sub(prec, Np - c1, kend - c1, NB_LEAF, lt(c1, c0 - k0), NB_OUT,
                                        at(c0, c1), lda, at(c1, c1), lda, f.flags, false, s));
             }
         }
+        HIPCHK(launch_gather_block(prec, Np, k0, kend, f.A, lda, f.xch, s));
         if (kend < Np) {
             HIPCHK(launch_lt_rebuild(prec, Np, k0, k0, kend - k0, f.A, lda, f.LT, s));
             for (int64_t c0 = k0; c0 < kend; c0 += NB_LEAF) {

@@ -176,13 +176,15 @@ hipError_t launch_gemm_sub(int prec, int64_t M, int64_t N, int64_t K, const void
                            int64_t ldat, const void *B, int64_t ldb, void *C, int64_t ldc,
                            int *flags, bool check_abort, hipStream_t s);
 // pivoting path: exchange area size (bytes), its reset, the cooperative leaf
-// panel, the row gather of its interchanges and the LT rebuild of an outer block
+// panel, the row moves of its interchanges, the LT rebuild of an outer block
 size_t pivot_xch_bytes(int prec, int64_t Np);
 hipError_t launch_pivot_reset(int prec, int64_t Np, void *xch, hipStream_t s);
 hipError_t launch_pivot_coop(int prec, int64_t Np, int64_t c0, int64_t k0, void *A, int64_t lda,
                              int32_t *ipiv, void *LT, void *xch, int *flags, hipStream_t s);
-hipError_t launch_row_gather(int prec, int64_t Np, int64_t c0, void *A, int64_t lda,
-                             const void *xch, hipStream_t s);
+hipError_t launch_gather_u12(int prec, int64_t Np, int64_t c0, int64_t k0, int64_t kend, void *A,
+                             int64_t lda, const void *xch, int *flags, hipStream_t s);
+hipError_t launch_gather_block(int prec, int64_t Np, int64_t k0, int64_t kend, void *A,
+                               int64_t lda, const void *xch, hipStream_t s);
 hipError_t launch_lt_rebuild(int prec, int64_t Np, int64_t r0, int64_t k0, int64_t ncol,
                              const void *A, int64_t lda, void *LT, hipStream_t s);
 hipError_t launch_u12(int prec, int64_t c0, int64_t col0, int64_t col1, void *A, int64_t lda,
