@@ -491,6 +491,28 @@ __device__ __forceinline__ void gemm16_tile(int row0, int col0, int K, const T *
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
 }
 
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8
+// XCDs (workgroup bid runs on XCD bid % 8), so give each XCD a contiguous run
+// of the tile sequence: XCD x owns tiles [start_x, start_x + count_x).  A
+// bijection for any tile count.
+__device__ __forceinline__ int xcd_tile(int bid, int nt)
+{
+    const int xcd = bid & 7, q8 = nt >> 3, r8 = nt & 7;
+    return xcd * q8 + (xcd < r8 ? xcd : r8) + (bid >> 3);
+}
+// Tile sequence -> (row tile, column tile) in groups of GM row tiles, so the
+// tiles an XCD's CUs hold at once share a few A row blocks and B column
+// blocks in its L2.
+__device__ __forceinline__ void grouped_tile(int tile, int ntm, int ntn, int &tm, int &tn)
+{
+    constexpr int GM = 8;
+    const int per_group = GM * ntn, group = tile / per_group, first_m = group * GM;
+    const int gsize = ntm - first_m < GM ? ntm - first_m : GM;
+    const int in_group = tile - group * per_group;
+    tm = first_m + in_group % gsize;
+    tn = in_group / gsize;
+}
+
 template <typename T, int TM, int TN, int WGM, int WGN, int KC>
 __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
                                                           const T *__restrict__ At, int64_t ldat,
@@ -499,20 +521,9 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16(int M, int N, int K,
                                                           int *__restrict__ flags, int check_abort)
 {
     if (check_abort && block_flag(&flags[FLAG_FAIL])) return;
-    const int ntm = M / TM, ntn = N / TN, nt = ntm * ntn;
-    const int bid = blockIdx.x;
-    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs;
-    // give each XCD a contiguous run of tiles, and order that run in groups
-    // of GM row tiles so the tiles an XCD's CUs hold at once share a few A
-    // row blocks and B column blocks in its L2.
-    // workgroup bid runs on XCD bid % 8; XCD x owns tiles [start_x, start_x + count_x)
-    const int xcd = bid & 7, q8 = nt >> 3, r8 = nt & 7;
-    const int tile = xcd * q8 + (xcd < r8 ? xcd : r8) + (bid >> 3);
-    constexpr int GM = 8;
-    const int per_group = GM * ntn, group = tile / per_group, first_m = group * GM;
-    const int gsize = ntm - first_m < GM ? ntm - first_m : GM;
-    const int in_group = tile - group * per_group;
-    const int tm = first_m + in_group % gsize, tn = in_group / gsize;
+    const int ntm = M / TM, ntn = N / TN;
+    int tm, tn;
+    grouped_tile(xcd_tile(blockIdx.x, ntm * ntn), ntm, ntn, tm, tn);
     gemm16_tile<T, TM, TN, WGM, WGN, KC>(tm * TM, tn * TN, K, At, ldat, B, ldb, C, ldc, flags);
 }
 
@@ -534,12 +545,12 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm16_pair(GemmProb p1, Gemm
                                                                int *__restrict__ flags)
 {
     if (block_flag(&flags[FLAG_FAIL])) return;
-    const int nt1 = (p1.M / TM) * (p1.N / TN);
-    int tile = blockIdx.x;
+    const int nt1 = (p1.M / TM) * (p1.N / TN), nt2 = (p2.M / TM) * (p2.N / TN);
+    int tile = xcd_tile(blockIdx.x, nt1 + nt2);
     const GemmProb &p = tile < nt1 ? p1 : p2;
     if (tile >= nt1) tile -= nt1;
-    const int ntm = p.M / TM;
-    const int tm = tile % ntm, tn = tile / ntm;
+    int tm, tn;
+    grouped_tile(tile, p.M / TM, p.N / TN, tm, tn);
     gemm16_tile<T, TM, TN, WGM, WGN, KC>(tm * TM, tn * TN, K, (const T *)p.At, p.ldat, (const T *)p.B,
                                          p.ldb, (T *)p.C, p.ldc, flags);
 }
