@@ -157,6 +157,31 @@ def test_getrf_singular_reports_info(env, n, zc):
     assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
 
 
+@pytest.mark.parametrize("n", [100, 1500])
+def test_getrf_nan_reported(env, n):
+    """A NaN in the matrix: the no-interchange check rejects it (NaN is never
+    within the pivot bound), the explicit search flags it, and the
+    factorisation reports a non-finite result (info = -1) instead of factors."""
+    n3p, torch = env
+    A = random_matrix(n, 8)
+    A[n // 2, n // 3] = np.nan
+    T = to_cm(torch, A, torch.float64)
+    ipiv, info = n3p.getrf(T)
+    assert info == -1
+
+
+def test_getrf_fp16_overflow_reported(env):
+    """Finite FP16 input whose partial-pivoting growth exceeds 65504: every
+    kernel checks the value it stores, so the overflow is reported (info = -1)."""
+    n3p, torch = env
+    n = 1024
+    A = np.clip(random_matrix(n, 9) * 1.5e4, -6.0e4, 6.0e4)
+    T = to_cm(torch, A, torch.float16)
+    assert torch.isfinite(T).all()
+    ipiv, info = n3p.getrf(T)
+    assert info == -1
+
+
 def test_getrf_fp64_pivoting_large_properties(env):
     """N = 16500 (more than 64 panel workgroups): partial pivoting's
     |L| <= 1 and the backward error of P A = L U, checked on the GPU.  The
