@@ -120,6 +120,21 @@ def cpu_baseline(n_sample: int, n_target: int, c: float):
                           n_sample, c, r.its, dt, n_target, n_sample, n_target)}
 
 
+def measured_mfma_peak(n3p, torch, prec, blocks=2048, iters=256):
+    """The matrix-core rate on this device (TFLOP/s): back-to-back 32x32x16
+    MFMA chains on register operands, timed with events on the current stream."""
+    n3p.mfma_rate_probe(prec, blocks, 8)  # warm-up (code load)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out, flops = n3p.mfma_rate_probe(prec, blocks, iters)
+    e1.record()
+    torch.cuda.synchronize()
+    if not bool((out == 2.0 * iters).all()):
+        raise RuntimeError("matrix-core rate probe returned wrong sums")
+    return flops / (e0.elapsed_time(e1) * 1e-3) / 1e12
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -157,9 +172,12 @@ def main():
         one()
     torch.cuda.synchronize()
     reps = []
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        reps.append(one())
+        ts = time.perf_counter()
+        reps.append(one())  # ends with the stopping test read on the host
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per = wall * 1e3 / args.steps
@@ -185,6 +203,7 @@ def main():
         "lin_its": rep.lin_its,
         "phase_ms_per_solve": {"jacobian": rep.ms_jac, "getrf": rep.ms_getrf,
                                "linear_solve": rep.ms_solve, "residual": rep.ms_resid},
+        "ms_per_step_median": float(np.median(step_ms)), "step_ms": step_ms,
         "getrf_ms": getrf_ms, "getrf_tflops": achieved,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_TFLOPS
                      if args.prec in ("FP16", "BF16") else PEAK_FP64_TFLOPS,
@@ -193,6 +212,10 @@ def main():
                      "traffic": measured_traffic(n, args.prec),
                      "kernel": "getrf (whole factorisation, (2/3)N^3 flop)", "padded_n": Np},
     }
+    if args.prec in ("FP16", "BF16"):
+        pk = measured_mfma_peak(n3p, torch, prec)
+        out["roofline"]["peak_measured"] = pk
+        out["roofline"]["frac_of_measured"] = achieved / pk if pk else None
     # the same solve with the O(N log N) residual and operator-based J v
     # (no stored FP32 Jacobian), for comparison
     if not args.no_mf:

@@ -231,6 +231,18 @@ N3P_API int n3p_getrf(int prec, int64_t n, void *A, int64_t lda, int32_t *ipiv, 
 N3P_API int n3p_getrs(int prec, int64_t n, const void *LU, int64_t lda, const int32_t *ipiv,
                       void *b, void *ws, size_t ws_bytes, void *stream);
 
+/* Measurement helper, not a step of the method: the rate the matrix cores
+ * reach on this device, against which the factorisation is also measured.
+ * Launches `blocks` workgroups of 256 threads (prec N3P_FP16 or N3P_BF16);
+ * every wavefront issues 8 independent chains of `iters` back-to-back
+ * 32x32x16 matrix-core instructions on register operands.  `out` (device,
+ * FP32, blocks * 256 entries, caller-owned) receives 2 * iters in every entry,
+ * which checks that the work was done; *flops (host) receives the number of
+ * floating-point operations issued.  iters in [1, 2^20].  Asynchronous on
+ * `stream`: time it with events.  N3P_E_INVALID for other arguments. */
+N3P_API int n3p_mfma_rate_probe(int prec, int blocks, int iters, float *out, double *flops,
+                                void *stream);
+
 /* r = b - A u for FP32 column-major A (n x n, leading dim lda) and FP32
  * vectors (device); products accumulate in FP64, r is rounded to FP32.  The
  * residual of the IR algorithm, Section 2.2.  Asynchronous. */

@@ -17,4 +17,5 @@ from ._binding import (  # noqa: F401
     getrf, getrs, gemv_resid, heq_residual, heq_jacobian, ir, gmres_ir,
     EngineConfig, ServeStats, Engine, serve, engine_request_bytes, engine_fixed_bytes,
     PHASE_FREE, PHASE_ADMITTED, PHASE_RUNNING, PHASE_DONE, heq_residual_fft, heq_jv,
+    mfma_rate_probe,
 )

@@ -135,9 +135,10 @@ def _setup():
                          _dp, _vp, ctypes.c_size_t, _vp]
     L.n3p_gmres_ir.argtypes = [_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _f64, _int,
                                _int, _f64, _ip, _ip, _ip, _dp, _vp, ctypes.c_size_t, _vp]
+    L.n3p_mfma_rate_probe.argtypes = [_int, _int, _int, _vp, _dp, _vp]
     for name in ("n3p_problem_heq", "n3p_problem_dense_tanh", "n3p_problem_callbacks",
                  "n3p_solve", "n3p_getrf", "n3p_getrs", "n3p_gemv_resid_f32", "n3p_heq_residual",
-                 "n3p_heq_jacobian", "n3p_ir", "n3p_gmres_ir"):
+                 "n3p_heq_jacobian", "n3p_ir", "n3p_gmres_ir", "n3p_mfma_rate_probe"):
         getattr(L, name).restype = _int
 
 
@@ -255,6 +256,17 @@ def getrs(LU: torch.Tensor, ipiv: torch.Tensor, b: torch.Tensor, prec: Optional[
     _check(lib.n3p_getrs(prec, n, _ptr(LU), n, _ptr(ipiv), _ptr(b), _ptr(ws), ws.numel(),
                          _stream()), "n3p_getrs")
     return b
+
+
+def mfma_rate_probe(prec: int = FP16, blocks: int = 1024, iters: int = 256,
+                    device="cuda"):
+    """n3p_mfma_rate_probe on the current stream; returns (out, flops).  Every
+    entry of `out` is 2*iters when the work was done; time it with events."""
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=device)
+    flops = ctypes.c_double(0.0)
+    _check(lib.n3p_mfma_rate_probe(prec, blocks, iters, _ptr(out), ctypes.byref(flops),
+                                   _stream()), "n3p_mfma_rate_probe")
+    return out, flops.value
 
 
 def gemv_resid(A: torch.Tensor, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:

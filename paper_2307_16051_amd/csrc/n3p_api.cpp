@@ -1221,6 +1221,16 @@ N3P_API int n3p_gemv_resid_f32(int64_t n, const float *A, int64_t lda, const flo
     return N3P_OK;
 }
 
+N3P_API int n3p_mfma_rate_probe(int prec, int blocks, int iters, float *out, double *flops,
+                                void *stream)
+{
+    if ((prec != N3P_FP16 && prec != N3P_BF16) || blocks < 1 || iters < 1 || iters > (1 << 20) ||
+        !out || !flops)
+        return N3P_E_INVALID;
+    HIPCHK(launch_mfma_rate(prec, blocks, iters, out, flops, (hipStream_t)stream));
+    return N3P_OK;
+}
+
 N3P_API int n3p_heq_residual(int64_t n, double c, const double *x, double *F, double *D,
                              void *stream)
 {

@@ -192,6 +192,10 @@ hipError_t launch_u12(int prec, int64_t c0, int64_t col0, int64_t col1, void *A,
 hipError_t launch_check_factor_finite(int prec, int64_t Np, const void *A, int64_t lda,
                                       int *flags, hipStream_t s);
 
+// measurement helper: the matrix-core rate (not a step of the method)
+hipError_t launch_mfma_rate(int prec, int blocks, int iters, float *out, double *flops,
+                            hipStream_t s);
+
 // triangular solves and matvec
 hipError_t launch_trsv_lower(int prec, int64_t n, const void *LU, int64_t lda, const int32_t *perm,
                              const float *b, float *y, int *sync, uint32_t epoch, int *flags,

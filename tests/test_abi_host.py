@@ -86,3 +86,17 @@ def test_matrix_free_workspace_drops_the_fp32_jacobian():
     assert abs((full - mf) - (4 * n * n - fft_bufs)) <= 2048
     # the FFT form is limited to N <= 32768
     assert n3p.workspace_size(40000, n3p.FP16, n3p.IR, n3p.Options.default(fft_residual=1)) == 0
+
+
+def test_mfma_rate_probe_rejects_bad_arguments(lib):
+    """Argument checks happen before any device call (no GPU here)."""
+    import ctypes
+    fl = ctypes.c_double(0.0)
+    buf = ctypes.c_void_p(1)  # never dereferenced: validation fails first
+    FP16, FP32 = 0, 2
+    assert lib.n3p_mfma_rate_probe(FP32, 1, 1, buf, ctypes.byref(fl), None) == -1
+    assert lib.n3p_mfma_rate_probe(FP16, 0, 1, buf, ctypes.byref(fl), None) == -1
+    assert lib.n3p_mfma_rate_probe(FP16, 1, 0, buf, ctypes.byref(fl), None) == -1
+    assert lib.n3p_mfma_rate_probe(FP16, 1, (1 << 20) + 1, buf, ctypes.byref(fl), None) == -1
+    assert lib.n3p_mfma_rate_probe(FP16, 1, 1, None, ctypes.byref(fl), None) == -1
+

@@ -220,6 +220,19 @@ def test_getrf_tie_break_lowest_row(env):
     assert ipiv.cpu().numpy()[0] == piv_ref[0] == 10
 
 
+@pytest.mark.parametrize("prec", ["FP16", "BF16"])
+def test_mfma_rate_probe_does_its_work(env, prec):
+    """The measurement helper: with every operand 1/32 each instruction adds
+    1/64 to every accumulator entry, so each lane's sum of 8 x 16 entries is
+    2 * iters exactly; the flop count is that of the instructions issued."""
+    n3p, torch = env
+    blocks, iters = 64, 100
+    out, flops = n3p.mfma_rate_probe(getattr(n3p, prec), blocks, iters)
+    torch.cuda.synchronize()
+    assert bool((out == 2.0 * iters).all())
+    assert flops == blocks * 4 * iters * 8 * (2 * 32 * 32 * 16)
+
+
 # ------------------------------------------------------------- solves
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 @pytest.mark.parametrize("n", [100, 700])
