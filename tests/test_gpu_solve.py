@@ -60,6 +60,42 @@ def test_heq_solve_matches_oracle(env, n, c, prec, solver):
     assert not any(rep.pivoted)
 
 
+@pytest.mark.parametrize("n,c", [(1, 0.5), (2, 0.9), (3, 0.99)])
+def test_tiny_systems_match_oracle(env, n, c):
+    """Sizes far below one 64-column leaf (the factorisation pads them to 512
+    with an identity block)."""
+    n3p, torch = env
+    print("case tiny heq n=%d c=%g" % (n, c), flush=True)
+    ref = O.newton_heq(n, c)
+    x, rep = n3p.solve_heq(n, c, prec=n3p.FP16, solver=n3p.IR)
+    assert rep.status == 0
+    assert rep.its in (ref.its, ref.its + 1)
+    assert rel_err(x.cpu().numpy(), ref.x_floor) <= 1e-9
+
+
+def test_c_zero_is_solved_at_x0(env):
+    """c = 0 reduces eq. (3.2) to H = 1: F(x0 = ones) = 0 exactly, so the
+    stopping test passes before any Newton step."""
+    n3p, torch = env
+    x, rep = n3p.solve_heq(300, 0.0)
+    assert rep.status == 0 and rep.its == 0
+    assert bool((x == 1.0).all())
+
+
+def test_maxit_reached_reports_not_converged(env):
+    """maxit = 1: one Newton step is taken, the status says not converged,
+    and the iterate is the first Newton iterate (to the accuracy of the
+    IR solve, eq. (2.13))."""
+    n3p, torch = env
+    n, c = 1000, 0.99
+    x, rep = n3p.solve_heq(n, c, opts=n3p.Options.default(maxit=1))
+    assert rep.status == 1 and rep.its == 1
+    ref = O.newton_heq(n, c, maxit=1, floor=False)
+    assert ref.its == 1
+    assert rel_err(x.cpu().numpy(), ref.x) <= 1e-4
+    assert rep.resid_rel[1] < 1.0   # the step reduced ||F||
+
+
 @pytest.mark.parametrize("n,cond,solver", [(512, 1e2, "IR"), (640, 1e4, "GMRES_IR")])
 def test_dense_tanh_pivoting_workload(env, n, cond, solver):
     n3p, torch = env
