@@ -155,15 +155,15 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
 #pragma unroll
                 for (int kk = 0; kk < 8; ++kk) {
                     const int k = 8 * p + kk;
+                    // branch-free (selects, no exec-mask branches): this is the
+                    // leaf's serial chain
                     const CT piv = lane_bcast(x[kk], k);
-                    if (!(fabs(piv) > (CT)0)) fail = true;
                     const CT rp = recip(piv);
-                    CT l = 0;
-                    if (r > k) {
-                        if (!(fabs(x[kk]) <= margin * fabs(piv))) fail = true;
-                        l = x[kk] * rp;
-                        x[kk] = l;
-                    }
+                    const bool below = r > k;
+                    const CT lx = x[kk] * rp;
+                    fail |= !(fabs(piv) > (CT)0) || (below && !(fabs(x[kk]) <= margin * fabs(piv)));
+                    const CT l = below ? lx : (CT)0;
+                    x[kk] = below ? lx : x[kk];
 #pragma unroll
                     for (int c = kk + 1; c < 8; ++c) x[c] -= l * lane_bcast(x[c], k);
                 }
@@ -237,10 +237,9 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
             const CT rd = rdiag[8 * kc + g];
 #pragma unroll
             for (int kq = 0; kq < 8; ++kq) {
-                if (g == kq) {
-                    if (!(fabs(x[0]) <= lim)) fail = true;
-                    x[0] *= rd;
-                }
+                const bool own = g == kq;  // branch-free, as in the diagonal chain
+                fail |= own && !(fabs(x[0]) <= lim);
+                x[0] = own ? x[0] * rd : x[0];
                 CT xk;
                 switch (kq) {
                 case 0: xk = oct_bcast<0>(x[0]); break;
