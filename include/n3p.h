@@ -105,8 +105,10 @@ typedef struct n3p_options {
                                 residual (default 1e-4) */
     int gmres_max_restarts;  /* restart cycles per GMRES call (default 10) */
     int scale_mode;          /* n3p_scale (default N3P_SCALE_AUTO) */
-    int timing;              /* 1: record per-phase times in the report (adds
-                                event records; default 1) */
+    int timing;              /* 1: record per-phase times in the report
+                                (timestamps written on the GPU timeline in
+                                the workspace, read once when the solve ends:
+                                no extra host waits; default 1) */
     int fft_residual;        /* built-in H-equation only: 1 = evaluate F by the
                                 O(N log N) FFT form of eq. (3.2) (the Hankel sum as
                                 a convolution, FP64); N <= 32768; default 0 */

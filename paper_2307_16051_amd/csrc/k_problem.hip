@@ -771,6 +771,20 @@ hipError_t launch_nrm2_f32(int64_t n, const float *x, double *part, double *out,
     return hipGetLastError();
 }
 
+// A timestamp on the GPU timeline (the 100 MHz real-time counter), for the
+// report's per-phase times without host synchronisation: one lane of one
+// wavefront writes it (a vector store).
+__global__ __launch_bounds__(64) void k_stamp(uint64_t *p)
+{
+    if (threadIdx.x == 0) *p = __builtin_amdgcn_s_memrealtime();
+}
+
+hipError_t launch_stamp(uint64_t *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int *p, int v, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);

@@ -264,12 +264,15 @@ struct SolveWs {
     double *H = nullptr, *ydev = nullptr;
     double *b64 = nullptr, *y64 = nullptr, *x64 = nullptr, *xs64 = nullptr;
     int *sync = nullptr;
+    uint64_t *stamps = nullptr;  // per-phase timestamps (NSTAMPS)
     // FFT form of the H-equation (fft_residual / matrix_free)
     int L = 0;
     bool fftres = false, mf = false;
     double2 *tw = nullptr, *Hh = nullptr, *t1 = nullptr, *t2 = nullptr, *W = nullptr;
     size_t bytes = 0;
 };
+
+constexpr int NSTAMPS = 1024;  // phase timestamps: <= 12 per Newton step, <= 64 steps
 
 size_t part_len_for(int64_t n)
 {
@@ -308,6 +311,7 @@ size_t solve_layout(int64_t n, int prec, int ls, int m, int fftmode, SolveWs *w,
         oxs64 = b.take((size_t)Np * 8);
     }
     size_t osync = b.take(trsv_sync_ints(Np) * 4);
+    size_t ostamp = b.take((size_t)NSTAMPS * 8);
     const int L = fftmode ? fft_length(n) : 0;
     size_t otw = 0, oHf = 0, ot1 = 0, ot2 = 0, oW = 0;
     if (L) {
@@ -342,6 +346,7 @@ size_t solve_layout(int64_t n, int prec, int ls, int m, int fftmode, SolveWs *w,
         w->part = (double *)(base + oP);
         w->part_len = pl;
         w->scal = (double *)(base + oS);
+        w->stamps = (uint64_t *)(base + ostamp);
         w->b = (float *)(base + ob);
         w->u = (float *)(base + ou);
         w->uprev = (float *)(base + oup);
@@ -727,23 +732,20 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = w.n;
 
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    if (opt.timing) {
-        HIPCHK(hipEventCreate(&ev[0]));
-        HIPCHK(hipEventCreate(&ev[1]));
-    }
     float t_jac = 0, t_getrf = 0, t_solve = 0, t_resid = 0;
+    // per-phase times: timestamps on the GPU timeline (no host wait), read
+    // once when the solve ends
+    int tslot = 0;
+    std::vector<std::pair<int, float *>> tpairs;
     auto tstart = [&]() -> int {
-        if (opt.timing) HIPCHK(hipEventRecord(ev[0], s));
+        if (opt.timing && tslot + 2 <= NSTAMPS) HIPCHK(launch_stamp(w.stamps + tslot, s));
         return 0;
     };
     auto tstop = [&](float *acc) -> int {
-        if (opt.timing) {
-            HIPCHK(hipEventRecord(ev[1], s));
-            HIPCHK(hipEventSynchronize(ev[1]));
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
-            *acc += ms;
+        if (opt.timing && tslot + 2 <= NSTAMPS) {
+            HIPCHK(launch_stamp(w.stamps + tslot + 1, s));
+            tpairs.emplace_back(tslot, acc);
+            tslot += 2;
         }
         return 0;
     };
@@ -913,9 +915,12 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
     HIPCHK(hipEventElapsedTime(&tot, e_all0, e_all1));
     hipEventDestroy(e_all0);
     hipEventDestroy(e_all1);
-    if (opt.timing) {
-        hipEventDestroy(ev[0]);
-        hipEventDestroy(ev[1]);
+    if (tslot > 0) {
+        std::vector<uint64_t> st((size_t)tslot);
+        HIPCHK(hipMemcpyAsync(st.data(), w.stamps, (size_t)tslot * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (const auto &pr : tpairs)
+            *pr.second += (float)((double)(st[pr.first + 1] - st[pr.first]) * STAMP_MS_PER_TICK);
     }
     if (rep) {
         rep->status = status;

@@ -145,6 +145,9 @@ hipError_t launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream
 hipError_t launch_nrm2_f64(int64_t n, const double *x, double *part, double *out, hipStream_t s);
 hipError_t launch_nrm2_f32(int64_t n, const float *x, double *part, double *out, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int v, int64_t n, hipStream_t s);
+// GPU-timeline timestamp (100 MHz real-time counter ticks) into *p
+hipError_t launch_stamp(uint64_t *p, hipStream_t s);
+constexpr double STAMP_MS_PER_TICK = 1e-5;
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
 // b = -F / ||F|| (FP64 in, FP32 out, padded tail zeroed up to np)

@@ -116,6 +116,19 @@ def test_dense_tanh_pivoting_workload(env, n, cond, solver):
     assert np.abs(xg - 1.0).max() <= 1e-9  # x* = 1 by construction
 
 
+def test_phase_times_add_up(env):
+    """The report's per-phase times come from GPU-timeline timestamps (100 MHz
+    real-time counter) read once at the end; they must lie within the
+    event-timed total and cover most of it."""
+    n3p, torch = env
+    x, rep = n3p.solve_heq(2048, 0.99)
+    phases = rep.ms_jac + rep.ms_getrf + rep.ms_solve + rep.ms_resid
+    print("  phases %.3f ms (jac %.3f getrf %.3f solve %.3f resid %.3f) total %.3f ms" % (
+        phases, rep.ms_jac, rep.ms_getrf, rep.ms_solve, rep.ms_resid, rep.ms_total), flush=True)
+    assert min(rep.ms_jac, rep.ms_getrf, rep.ms_solve, rep.ms_resid) > 0
+    assert 0.5 * rep.ms_total <= phases <= 1.02 * rep.ms_total
+
+
 def test_table2_three_precision_history_at_paper_size(env, table2):
     """N=4096, c=.99: FP16 LU + IR, histories vs the printed IR 32-16 column."""
     n3p, torch = env
