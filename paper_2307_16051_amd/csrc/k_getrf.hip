@@ -94,11 +94,12 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
     constexpr int LP = L + 4;
     constexpr int NT = LEAF_THREADS;
     __shared__ __attribute__((aligned(16))) CT Dm[L][LP];       // diagonal block
-    // Ui[k][g][c] = U[k][8c+g], Li[k][g][u] = L[8u+g][k] where that index
-    // exceeds k, else 0; flat with 8 trailing entries so reads for register
-    // slots past index 63 stay in the array (those slots are dead).
-    __shared__ __attribute__((aligned(16))) CT Ui[L * L + 8];
-    __shared__ __attribute__((aligned(16))) CT Li[L * L + 8];
+    // Per column group kc of the tile solves: Ui[kc][kq][g][c] =
+    // U[8kc+kq][8(kc+c)+g] and Li[kc][kq][g][u] = L[8(kc+u)+g][8kc+kq] where
+    // kc + c <= 7 and that index exceeds the row (column) 8kc+kq, else 0 -- so
+    // a lane's 8 coefficients of one step are contiguous and 16-byte aligned.
+    __shared__ __attribute__((aligned(16))) CT Ui[L * L];
+    __shared__ __attribute__((aligned(16))) CT Li[L * L];
     __shared__ __attribute__((aligned(16))) CT Sg[L][LP];       // staging of one tile
     __shared__ CT rdiag[L];
     __shared__ int sfail;
@@ -188,10 +189,10 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
         if (t == 0) set_flag(&flags[FLAG_FAIL], 1);
         return;
     }
-    for (int e = t; e < L * L + 8; e += NT) {
-        const int k = e / L, m = e % L;
-        const int g = m / 8, c = m % 8, j = 8 * c + g;
-        const bool in = e < L * L && j > k;
+    for (int e = t; e < L * L; e += NT) {
+        const int c = e % 8, g = (e / 8) % 8, kq = (e / 64) % 8, kc = e / 512;
+        const int k = 8 * kc + kq, j = 8 * (kc + c) + g;
+        const bool in = kc + c <= 7 && j > k;
         Ui[e] = in ? Dm[k][j] : (CT)0;
         Li[e] = in ? Dm[j][k] : (CT)0;
     }
@@ -231,7 +232,7 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
 #pragma unroll
             for (int kq = 0; kq < 8; ++kq)
 #pragma unroll
-                for (int c = 0; c < 8; ++c) u[kq][c] = Ui[(8 * kc + kq) * L + g * 8 + kc + c];
+                for (int c = 0; c < 8; ++c) u[kq][c] = Ui[((kc * 8 + kq) * 8 + g) * 8 + c];
             // this lane owns column 8kc + g: its pivot bound and reciprocal
             const CT lim = margin * fabs(Dm[8 * kc + g][8 * kc + g]);
             const CT rd = rdiag[8 * kc + g];
@@ -300,7 +301,7 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
 #pragma unroll
             for (int kq = 0; kq < 8; ++kq)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) lv[kq][u] = Li[(8 * ku + kq) * L + g * 8 + ku + u];
+                for (int u = 0; u < 8; ++u) lv[kq][u] = Li[((ku * 8 + kq) * 8 + g) * 8 + u];
 #pragma unroll
             for (int kq = 0; kq < 8; ++kq) {
                 CT yk;
