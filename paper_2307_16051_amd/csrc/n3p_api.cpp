@@ -214,13 +214,20 @@ int getrf_pivot(const FactorWs &f, hipStream_t s)
 }
 
 // Factor f.A in place.  `refill` restores the unfactored matrix into f.A
-// (needed when the no-interchange attempt is abandoned).
+// (needed when the no-interchange attempt is abandoned).  `xdev` (optional):
+// one double copied to *xhost in the same host wait as the flags (work the
+// caller queued before the factorisation).
 template <typename Refill>
-int getrf_run(const FactorWs &f, hipStream_t s, Refill refill, FactorResult *res)
+int getrf_run(const FactorWs &f, hipStream_t s, Refill refill, FactorResult *res,
+              const double *xdev = nullptr, double *xhost = nullptr)
 {
     int h[NFLAGS];
     HIPCHK(launch_fill_i32(f.flags, 0, NFLAGS, s));
     CHK(getrf_spec(f, s));
+    // identity interchanges, queued before the wait (the pivoting path
+    // overwrites every entry if it runs)
+    HIPCHK(launch_iota_i32(f.ipiv, f.Np, s));
+    if (xdev) HIPCHK(hipMemcpyAsync(xhost, xdev, sizeof(double), hipMemcpyDeviceToHost, s));
     CHK(read_flags(f, s, h));
     res->pivoted = false;
     if (h[FLAG_FAIL]) {
@@ -241,8 +248,6 @@ int getrf_run(const FactorWs &f, hipStream_t s, Refill refill, FactorResult *res
         }
         HIPCHK(hipMemcpyAsync(f.perm, pm.data(), f.Np * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
-    } else {
-        HIPCHK(launch_iota_i32(f.ipiv, f.Np, s));
     }
     res->info = h[FLAG_ZEROPIV];
     res->nonfinite = h[FLAG_NONFINITE] != 0;
@@ -526,13 +531,19 @@ int gmres_lp(LinCtx &c, const float *r, float *d, int m, double rtol, int max_re
 // 3.1): r = b - A u; repeat { d = correction(r); u += d; r = b - A u } until
 // ||r|| < tol ||b|| (success), the sweep cap, or ||r|| grows (failure: the
 // previous, best, iterate is restored).
+// nb_pre (optional): ||b||, with u = 0 and r = b already in place (queued by
+// the caller ahead of the factorisation).
 int refine(LinCtx &c, const float *b, float *u, double tol, int max_sweeps, bool zero_start,
-           bool gmres, int m, double gtol, int max_restarts, LinOut *o)
+           bool gmres, int m, double gtol, int max_restarts, LinOut *o,
+           const double *nb_pre = nullptr)
 {
     double nb = 0.0;
-    CHK(norm32(c, b, &nb));
+    if (nb_pre) nb = *nb_pre;
+    else CHK(norm32(c, b, &nb));
     double rn = nb;
-    if (zero_start) {
+    if (nb_pre) {
+        // u = 0 and r = b were set with ||b||
+    } else if (zero_start) {
         HIPCHK(launch_fill_f32(u, 0.0f, c.n, c.s));
         HIPCHK(launch_vcopy_f32(c.n, c.r, b, c.s));
     } else {
@@ -820,7 +831,18 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
     // lower targets are kept for the rest of the solve (the Jacobian changes
     // little from one Newton step to the next, so its growth does too).
     float tl = 9.0f;
+    // IR and GMRES-IR: b = -F/||F||, ||b||, u = 0 and r = b depend on F only,
+    // so they are queued ahead of the Jacobian and the factorisation, and
+    // ||b|| comes back in the factorisation's flag read (no extra host wait)
+    const bool pre_rhs = ls != N3P_DIRECT;
     while (fn > tau && its < opt.maxit) {
+        double nb_pre = 0.0;
+        if (pre_rhs) {
+            HIPCHK(launch_rhs_unit(n, w.Np, w.F, w.scal, w.b, s));
+            HIPCHK(launch_nrm2_f32(n, w.b, w.part, lc.scal, s));
+            HIPCHK(launch_fill_f32(w.u, 0.0f, n, s));
+            HIPCHK(launch_vcopy_f32(n, lc.r, w.b, s));
+        }
         // --- J = F'(x) stored FP32, J_h = I_s^h(J) (column scaled for FP16)
         bool scaled = want_scale;
         FactorResult fr;
@@ -838,7 +860,7 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
                                           scaled ? w.colscale : nullptr, tl, w.f.flags, s));
                 return 0;
             };
-            CHK(getrf_run(w.f, s, refill, &fr));
+            CHK(getrf_run(w.f, s, refill, &fr, pre_rhs ? lc.scal : nullptr, &nb_pre));
             CHK(tstop(&t_getrf));
             if (fr.timeout) return N3P_E_TIMEOUT;
             if (fr.nonfinite && want_scale && attempt == 0 && tl > 3.0f) {
@@ -867,7 +889,7 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
             lo.inner = 1;
             HIPCHK(launch_newton_update_f64(n, x, fnd, w.x64, s));
         } else {
-            HIPCHK(launch_rhs_unit(n, w.Np, w.F, fnd, w.b, s));
+            if (!pre_rhs) HIPCHK(launch_rhs_unit(n, w.Np, w.F, fnd, w.b, s));
             if (ls == N3P_DIRECT) {
                 CHK(apply_prec(lc, w.b, w.u));
                 lo.sweeps = 1;
@@ -879,7 +901,7 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
                 lo.rel = nb > 0 ? rn / nb : 0;
             } else {
                 CHK(refine(lc, w.b, w.u, opt.eta, opt.max_ir_sweeps, true, ls == N3P_GMRES_IR, m,
-                           opt.gmres_tol, opt.gmres_max_restarts, &lo));
+                           opt.gmres_tol, opt.gmres_max_restarts, &lo, &nb_pre));
             }
             HIPCHK(launch_newton_update_f32(n, x, fnd, w.u, s));
         }
