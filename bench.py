@@ -277,20 +277,31 @@ def fp64_baseline(n3p, torch, dev, n, c, x, getrf_flops, ms_per, out):
         out["fp64_lu_newton"]["rocsolver_getrf_ms"] = "unavailable: %s" % type(e).__name__
 
 
+def factor_source_sha(root=ROOT):
+    """SHA-256 over what decides the factorisation's memory traffic: the
+    kernel source (k_getrf.hip) and the launch schedule (getrf_spec)."""
+    import hashlib
+    csrc = os.path.join(root, "paper_2307_16051_amd", "csrc")
+    api = open(os.path.join(csrc, "n3p_api.cpp")).read()
+    i = api.index("int getrf_spec(")
+    sched = api[i:api.index("\n}\n", i)]
+    h = hashlib.sha256(open(os.path.join(csrc, "k_getrf.hip"), "rb").read())
+    h.update(sched.encode())
+    return h.hexdigest()
+
+
 def measured_traffic(n, prec):
     """HBM bytes per factorisation from the committed rocprofv3 counter runs
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), only if
-    the factorisation kernels' source is unchanged since they were taken."""
-    import hashlib
+    the factorisation's kernels and launch schedule are unchanged since they
+    were taken."""
     path = os.path.join(ROOT, "profiles", "getrf_traffic_n%d_%s.json" % (n, prec.lower()))
-    src = os.path.join(ROOT, "paper_2307_16051_amd", "csrc", "k_getrf.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = factor_source_sha()
     except (OSError, ValueError):
         return None
-    return rec.get("bytes_per_factorisation") if rec.get("k_getrf_sha256") == sha else None
-
+    return rec.get("bytes_per_factorisation") if rec.get("factor_source_sha256") == sha else None
 
 if __name__ == "__main__":
     main()

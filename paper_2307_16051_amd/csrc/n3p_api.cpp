@@ -115,6 +115,11 @@ int read_flags(const FactorWs &f, hipStream_t s, int *h)
 }
 
 // No-interchange attempt (verified against the partial-pivoting rule).
+// Three levels of right-looking updates: after each 64-column leaf the rest
+// of its 256-column middle block (below) and the middle block's rows to the
+// right (to the end of the matrix); after each middle block, K = 256, the
+// rest of the 1024-column outer block (below) and the outer block's rows to
+// its right; after each outer block, K = 1024, the trailing matrix.
 int getrf_spec(const FactorWs &f, hipStream_t s)
 {
     const int prec = f.prec;
@@ -124,34 +129,41 @@ int getrf_spec(const FactorWs &f, hipStream_t s)
     char *LT = (char *)f.LT;
     char *DG = (char *)f.DG;
     const size_t dgb = (size_t)NB_LEAF * NB_LEAF * es;
+    const bool mfma16 = prec == N3P_FP16 || prec == N3P_BF16;
     auto at = [&](int64_t i, int64_t j) { return (void *)(A + ((size_t)i + (size_t)j * lda) * es); };
+    // C(r0.., c0..) of the two updates (r0 = first row below the source
+    // panel, [cb, ce) its block's columns): the rest of the block below the
+    // panel, and the block's rows right of the block.  At: LT rows from r0,
+    // K columns from kc within the outer block; B: the panel's U rows.
+    auto update = [&](int64_t r0, int64_t ce, int64_t prow, int64_t kc, int64_t K) -> int {
+        const void *At = LT + ((size_t)r0 * NB_OUT + (size_t)kc) * es;
+        if (mfma16) {
+            HIPCHK(launch_gemm_pair(prec, Np - r0, ce - r0, At, NB_OUT, at(prow, r0), lda,
+                                    at(r0, r0), lda, ce - r0, Np - ce, At, NB_OUT, at(prow, ce),
+                                    lda, at(r0, ce), lda, K, f.flags, s));
+        } else {
+            HIPCHK(launch_gemm_sub(prec, Np - r0, ce - r0, K, At, NB_OUT, at(prow, r0), lda,
+                                   at(r0, r0), lda, f.flags, true, s));
+            if (ce < Np)
+                HIPCHK(launch_gemm_sub(prec, ce - r0, Np - ce, K, At, NB_OUT, at(prow, ce), lda,
+                                       at(r0, ce), lda, f.flags, true, s));
+        }
+        return 0;
+    };
     for (int64_t k0 = 0; k0 < Np; k0 += NB_OUT) {
         const int64_t kend = std::min<int64_t>(k0 + NB_OUT, Np);
-        for (int64_t c0 = k0; c0 < kend; c0 += NB_LEAF) {
-            const int64_t leaf = c0 / NB_LEAF;
-            void *dg = DG + (leaf % 2) * dgb;
-            const void *dgp = leaf > 0 ? DG + ((leaf - 1) % 2) * dgb : nullptr;
-            HIPCHK(launch_leaf_spec2(prec, Np, c0, f.A, lda, f.LT, k0, dg, dgp, c0 - NB_LEAF,
-                                     f.flags, s));
-            const int64_t c1 = c0 + NB_LEAF;
-            if (c1 < kend) {
-                const void *At = LT + ((size_t)c1 * NB_OUT + (size_t)(c0 - k0)) * es;
-                if (prec == N3P_FP16 || prec == N3P_BF16) {
-                    // rest of the outer panel (below) and rest of the outer row
-                    // block (right of the panel): one launch
-                    HIPCHK(launch_gemm_pair(prec, Np - c1, kend - c1, At, NB_OUT, at(c0, c1), lda,
-                                            at(c1, c1), lda, kend - c1, Np - kend, At, NB_OUT,
-                                            at(c0, kend), lda, at(c1, kend), lda, NB_LEAF, f.flags,
-                                            s));
-                } else {
-                    HIPCHK(launch_gemm_sub(prec, Np - c1, kend - c1, NB_LEAF, At, NB_OUT,
-                                           at(c0, c1), lda, at(c1, c1), lda, f.flags, true, s));
-                    if (kend < Np)
-                        HIPCHK(launch_gemm_sub(prec, kend - c1, Np - kend, NB_LEAF, At, NB_OUT,
-                                               at(c0, kend), lda, at(c1, kend), lda, f.flags, true,
-                                               s));
-                }
+        for (int64_t m0 = k0; m0 < kend; m0 += NB_MID) {
+            const int64_t mend = std::min<int64_t>(m0 + NB_MID, kend);
+            for (int64_t c0 = m0; c0 < mend; c0 += NB_LEAF) {
+                const int64_t leaf = c0 / NB_LEAF;
+                void *dg = DG + (leaf % 2) * dgb;
+                const void *dgp = leaf > 0 ? DG + ((leaf - 1) % 2) * dgb : nullptr;
+                HIPCHK(launch_leaf_spec2(prec, Np, c0, f.A, lda, f.LT, k0, dg, dgp, c0 - NB_LEAF,
+                                         f.flags, s));
+                const int64_t c1 = c0 + NB_LEAF;
+                if (c1 < mend) CHK(update(c1, mend, c0, c0 - k0, NB_LEAF));
             }
+            if (mend < kend) CHK(update(mend, kend, m0, m0 - k0, mend - m0));
         }
         if (kend < Np) {
             const void *At = LT + (size_t)kend * NB_OUT * es;

@@ -24,6 +24,7 @@ namespace n3p {
 constexpr int NB_OUT = 1024;  // outer block: K of the big Schur-complement GEMM
 constexpr int NB_PAD = 512;   // factorisation sizes are padded to a multiple of this
 constexpr int NB_LEAF = 64;   // leaf panel width
+constexpr int NB_MID = 256;   // middle level: leaves' rank-64 updates stay inside it
 constexpr int TRSV_BS = 64;   // row block of the triangular solves
 constexpr int FLAG_FAIL = 0, FLAG_NONFINITE = 1, FLAG_ZEROPIV = 2, FLAG_TIMEOUT = 3;
 constexpr int NFLAGS = 16;
