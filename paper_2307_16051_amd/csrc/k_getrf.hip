@@ -464,28 +464,38 @@ __device__ __forceinline__ void gemm16_tile(int row0, int col0, int K, const T *
 #undef N3P_GLOAD
 #undef N3P_SSTORE
 
-    // epilogue: lane holds column (lane & 31) and rows 8g + 4(lane >> 5) + q
+    // epilogue: lane holds column (lane & 31) and rows 8g + 4(lane >> 5) + q.
+    // Every C load of the wave is issued before the first store, so the
+    // read-modify-write costs one memory round trip, not one per fragment
+    // (the compiler cannot move a load past a store to the same array).
     typedef T t4 __attribute__((ext_vector_type(4)));
+    t4 cv[FM][FN][4];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            const T *cp = C + (int64_t)(col0 + wn * WN + fn * 32 + lr) * ldc + row0 + wm * WM +
+                          fm * 32 + (lane >> 5) * 4;
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) cv[fm][fn][gq] = *(const t4 *)(cp + gq * 8);
+        }
     bool bad = false;
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn) {
-            const int col = col0 + wn * WN + fn * 32 + lr;
-            const int rb0 = row0 + wm * WM + fm * 32 + (lane >> 5) * 4;
-            T *cp = C + (int64_t)col * ldc;
+            T *cp = C + (int64_t)(col0 + wn * WN + fn * 32 + lr) * ldc + row0 + wm * WM + fm * 32 +
+                    (lane >> 5) * 4;
 #pragma unroll
             for (int gq = 0; gq < 4; ++gq) {
-                t4 *p = (t4 *)(cp + rb0 + gq * 8);
-                t4 cv = *p;
                 t4 o;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float v = (float)cv[q] - acc[fm][fn][gq * 4 + q];
+                    const float v = (float)cv[fm][fn][gq][q] - acc[fm][fn][gq * 4 + q];
                     o[q] = (T)v;
                     bad |= !isfinite((float)o[q]);
                 }
-                *p = o;
+                *(t4 *)(cp + gq * 8) = o;
             }
         }
     if (bad) set_flag(&flags[FLAG_NONFINITE], 1);
