@@ -4,10 +4,12 @@
 // Triangular solves: one persistent launch per solve.  Row blocks of BS rows
 // are taken in dependency order through an atomic ticket (a block only waits
 // on blocks with smaller tickets, which are already running, so the waits
-// always end).  Block i accumulates the contributions of finished blocks as
-// they are published, then substitutes its diagonal block in one wavefront
-// and publishes its piece of the solution with a per-block flag holding the
-// launch's epoch (no flag reset between launches).  Factors are read in their
+// always end).  Block i inverts its diagonal block and premultiplies the
+// tile of its nearest predecessor by that inverse while the chain is still
+// far away, accumulates the contributions of the other finished blocks as
+// they are published, and once its nearest predecessor publishes, finishes
+// with one BS x BS product and publishes its piece of the solution as words
+// stamped with the launch's epoch (no flag reset between launches).  Factors are read in their
 // storage precision and promoted in registers (interprecision transfer on
 // the fly, Section 2.3).  Every wait is bounded; an expired wait raises
 // FLAG_TIMEOUT and the block proceeds so that the grid always drains.
@@ -155,11 +157,80 @@ __device__ __forceinline__ void load_tile_row(V (&fv)[BS], const T *__restrict__
     for (int c = 0; c < BS; ++c) fv[c] = c0 + c < n ? (V)to_f32(raw[c]) : (V)0;
 }
 
+// Diagonal-block helpers.  Each block inverts its own BS x BS diagonal block
+// D (held row-major, stride BS, in Dr) and forms Mx = D^{-1} E, with E the
+// neighbouring off-diagonal tile it depends on last (stride BS, in Eb).  Then
+// only one product with the neighbour's solution is left after it arrives:
+// lower x_b = D^{-1} (b_b - sum_{j<b-1} L_bj x_j) - D^{-1} L_{b,b-1} x_{b-1},
+// upper x_b = D^{-1} (y_b - sum_{j>b+1} U_bj x_j) - D^{-1} U_{b,b+1} x_{b+1}.
+// (Rounding differs from substitution only in the order of the sums.)
+//
+// Inverse of the diagonal block, wavefront 0, lane c = column c of the
+// inverse (LOWER: unit lower; else upper with reciprocals rd of its
+// diagonal).  Dr entries on or beyond the diagonal's wrong side are ignored.
+template <typename V, int BS, bool LOWER>
+__device__ __forceinline__ void diag_inverse(const V *__restrict__ Dr, const V *__restrict__ rd,
+                                             V *__restrict__ Di, int lane)
+{
+    V xi[BS];
+    if constexpr (LOWER) {
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+            V v = lane == i ? (V)1 : (V)0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) v -= Dr[i * BS + k] * xi[k];
+            xi[i] = v;
+        }
+    } else {
+#pragma unroll
+        for (int i = BS - 1; i >= 0; --i) {
+            V v = lane == i ? (V)1 : (V)0;
+#pragma unroll
+            for (int k = i + 1; k < BS; ++k) v -= Dr[i * BS + k] * xi[k];
+            xi[i] = v * rd[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < BS; ++i) Di[i * (BS + 1) + lane] = xi[i];
+}
+
+// Mx = Di Eb (BS x BS each), all four wavefronts: lane = row, wavefront wv
+// = columns 16 wv .. 16 wv + 15.  Di stride BS + 1, Eb stride BS, Mx stride BS + 1.
+template <typename V, int BS>
+__device__ __forceinline__ void diag_times_tile(const V *__restrict__ Di, const V *__restrict__ Eb,
+                                                V *__restrict__ Mx, int lane, int wv)
+{
+    constexpr int CW = BS / 4;
+    V m[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) m[c] = 0;
+#pragma unroll 8
+    for (int k = 0; k < BS; ++k) {
+        const V d = Di[lane * (BS + 1) + k];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) m[c] += d * Eb[k * BS + wv * CW + c];
+    }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) Mx[lane * (BS + 1) + wv * CW + c] = m[c];
+}
+
+// sum_c R[lane][c] v[c] with v held one value per lane (R stride BS + 1),
+// four independent partial sums.
+template <typename V, int BS>
+__device__ __forceinline__ V row_times_lanes(const V *__restrict__ R, V v, int lane)
+{
+    V a[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < BS; ++c) a[c & 3] += R[lane * (BS + 1) + c] * lane_bcast(v, c);
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
 // ---------------------------------------------------------------- lower
 // y = L^{-1} (P b): L unit lower (below the diagonal of LU), perm[i] = the
 // original row placed at position i (null = identity).  Block `blk` owns rows
-// [blk*BS, blk*BS + BS) (lane = row); wavefront w consumes tiles w, w+4, ...,
-// keeping the next tile's loads in flight while it consumes the current one.
+// [blk*BS, blk*BS + BS) (lane = row); wavefront w consumes tiles w, w+4, ...
+// below blk - 1, keeping the next tile's loads in flight while it consumes
+// the current one.  Tile blk - 1 enters through Mx = D^{-1} L_{b,b-1}.
 template <typename T, typename V, int BS>
 __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restrict__ LU, int64_t lda,
                                                     const int32_t *__restrict__ perm,
@@ -169,7 +240,9 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
 {
     static_assert(BS == 64, "a wavefront spans one tile");
     __shared__ int s_blk;
-    __shared__ V Dg[BS][BS + 1];
+    __shared__ __attribute__((aligned(16))) V Dr[BS * (BS + 1)];  // D (stride BS), then Mx (stride BS + 1)
+    __shared__ __attribute__((aligned(16))) V Eb[BS * BS];        // L_{b,b-1}
+    __shared__ V Di[BS * (BS + 1)];                               // D^{-1}
     __shared__ V part[4][BS];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) s_blk = __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -177,10 +250,6 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
     const int blk = s_blk;
     uint64_t *tags = tag_words(sync);
     const int64_t r0 = (int64_t)blk * BS;
-    for (int e = tid; e < BS * BS; e += 256) {
-        const int i = e % BS, j = e / BS;
-        Dg[i][j] = (j < i && r0 + i < n) ? (V)to_f32(LU[(r0 + i) + (r0 + j) * lda]) : (V)0;
-    }
     const int64_t row = r0 + lane;
     const bool rv = row < n;
     const int64_t rowc = rv ? row : 0;
@@ -188,14 +257,25 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
     int spins = 0;
     V fv[BS], fvn[BS];
     lane_word<V> cur, nxt;
+    const int last = blk - 1;  // tiles jb < last go through the loop
+    for (int e = tid; e < BS * BS; e += 256) {
+        const int i = e % BS, j = e / BS;
+        const bool in = r0 + i < n;
+        Dr[i * BS + j] = (j < i && in) ? (V)to_f32(LU[(r0 + i) + (r0 + j) * lda]) : (V)0;
+        if (blk > 0) Eb[i * BS + j] = in ? (V)to_f32(LU[(r0 + i) + (r0 - BS + j) * lda]) : (V)0;
+    }
+    __syncthreads();
+    if (wv == 0) diag_inverse<V, BS, true>(Dr, nullptr, Di, lane);
+    __syncthreads();
+    if (blk > 0) diag_times_tile<V, BS>(Di, Eb, Dr, lane, wv);
     int jb = wv;
-    if (jb < blk) {
+    if (jb < last) {
         load_tile_row<T, V, BS>(fv, LU, lda, rowc, (int64_t)jb * BS, n);
         cur.issue(tags, (int64_t)jb * BS + lane, true);
     }
-    for (; jb < blk; jb += 4) {
+    for (; jb < last; jb += 4) {
         const int nj = jb + 4;
-        if (nj < blk) {
+        if (nj < last) {
             load_tile_row<T, V, BS>(fvn, LU, lda, rowc, (int64_t)nj * BS, n);
             nxt.issue(tags, (int64_t)nj * BS + lane, true);
         }
@@ -213,11 +293,16 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
             const int64_t src = perm ? (int64_t)perm[row] : row;
             z = b[src] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
         }
-#pragma unroll
-        for (int c = 0; c < BS; ++c) z -= Dg[lane][c] * lane_bcast(z, c);
+        V w = row_times_lanes<V, BS>(Di, z, lane);
+        if (blk > 0) {
+            lane_word<V> xp;
+            xp.issue(tags, (int64_t)last * BS + lane, true);
+            xp.settle(tags, (int64_t)last * BS + lane, true, epoch, &spins, flags);
+            w -= row_times_lanes<V, BS>(Dr, xp.value(), lane);
+        }
         if (rv) {
-            y[row] = z;
-            tagged<V>::put(tags, row, z, epoch);
+            y[row] = w;
+            tagged<V>::put(tags, row, w, epoch);
         }
     }
 }
@@ -225,6 +310,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
 // ---------------------------------------------------------------- upper
 // x = S U^{-1} y with S = diag(colscale) (null = identity).  Blocks run from
 // the last to the first; other blocks read the unscaled solution (tagged).
+// Tile blk + 1 enters through Mx = D^{-1} U_{b,b+1}.
 template <typename T, typename V, int BS>
 __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restrict__ LU, int64_t lda,
                                                     const V *__restrict__ yin,
@@ -234,7 +320,9 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
 {
     static_assert(BS == 64, "a wavefront spans one tile");
     __shared__ int s_blk;
-    __shared__ V Dg[BS][BS + 1];
+    __shared__ __attribute__((aligned(16))) V Dr[BS * (BS + 1)];  // D (stride BS), then Mx (stride BS + 1)
+    __shared__ __attribute__((aligned(16))) V Eb[BS * BS];        // U_{b,b+1}
+    __shared__ V Di[BS * (BS + 1)];                               // D^{-1}
     __shared__ V rd[BS];
     __shared__ V part[4][BS];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -244,13 +332,6 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
     const int blk = s_blk;
     uint64_t *tags = tag_words(sync);
     const int64_t r0 = (int64_t)blk * BS;
-    for (int e = tid; e < BS * BS; e += 256) {
-        const int i = e % BS, j = e / BS;
-        const bool in = r0 + i < n && r0 + j < n;
-        const V u = in ? (V)to_f32(LU[(r0 + i) + (r0 + j) * lda]) : (V)0;
-        Dg[i][j] = j > i ? u : (V)0;
-        if (i == j) rd[i] = in ? (V)1 / u : (V)1;
-    }
     const int64_t row = r0 + lane;
     const bool rv = row < n;
     const int64_t rowc = rv ? row : 0;
@@ -258,14 +339,31 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
     int spins = 0;
     V fv[BS], fvn[BS];
     lane_word<V> cur, nxt;
+    const int next = blk + 1;  // tiles jb > next go through the loop
+    const bool has_next = next < nb;
+    for (int e = tid; e < BS * BS; e += 256) {
+        const int i = e % BS, j = e / BS;
+        const bool in = r0 + i < n && r0 + j < n;
+        const V u = in ? (V)to_f32(LU[(r0 + i) + (r0 + j) * lda]) : (V)0;
+        Dr[i * BS + j] = j > i ? u : (V)0;
+        if (i == j) rd[i] = in ? (V)1 / u : (V)1;
+        if (has_next) {
+            const bool in2 = r0 + i < n && r0 + BS + j < n;
+            Eb[i * BS + j] = in2 ? (V)to_f32(LU[(r0 + i) + (r0 + BS + j) * lda]) : (V)0;
+        }
+    }
+    __syncthreads();
+    if (wv == 0) diag_inverse<V, BS, false>(Dr, rd, Di, lane);
+    __syncthreads();
+    if (has_next) diag_times_tile<V, BS>(Di, Eb, Dr, lane, wv);
     int jb = nb - 1 - wv;
-    if (jb > blk) {
+    if (jb > next) {
         load_tile_row<T, V, BS>(fv, LU, lda, rowc, (int64_t)jb * BS, n);
         cur.issue(tags, (int64_t)jb * BS + lane, (int64_t)jb * BS + lane < n);
     }
-    for (; jb > blk; jb -= 4) {
+    for (; jb > next; jb -= 4) {
         const int nj = jb - 4;
-        if (nj > blk) {
+        if (nj > next) {
             load_tile_row<T, V, BS>(fvn, LU, lda, rowc, (int64_t)nj * BS, n);
             nxt.issue(tags, (int64_t)nj * BS + lane, true);
         }
@@ -279,16 +377,18 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
     part[wv][lane] = acc;
     __syncthreads();
     if (wv == 0) {
-        V z = rv ? yin[row] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) : (V)0;
-        const V rdl = rd[lane];
-#pragma unroll
-        for (int c = BS - 1; c >= 0; --c) {
-            if (lane == c) z *= rdl;
-            z -= Dg[lane][c] * lane_bcast(z, c);
+        const V z = rv ? yin[row] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) : (V)0;
+        V w = row_times_lanes<V, BS>(Di, z, lane);
+        if (has_next) {
+            const bool valid = (int64_t)next * BS + lane < n;
+            lane_word<V> xn;
+            xn.issue(tags, (int64_t)next * BS + lane, valid);
+            xn.settle(tags, (int64_t)next * BS + lane, valid, epoch, &spins, flags);
+            w -= row_times_lanes<V, BS>(Dr, valid ? xn.value() : (V)0, lane);
         }
         if (rv) {
-            tagged<V>::put(tags, row, z, epoch);
-            x[row] = colscale ? z * (V)colscale[row] : z;
+            tagged<V>::put(tags, row, w, epoch);
+            x[row] = colscale ? w * (V)colscale[row] : w;
         }
     }
 }
