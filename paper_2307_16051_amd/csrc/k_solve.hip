@@ -214,15 +214,21 @@ __device__ __forceinline__ void diag_times_tile(const V *__restrict__ Di, const 
     for (int c = 0; c < CW; ++c) Mx[lane * (BS + 1) + wv * CW + c] = m[c];
 }
 
-// sum_c R[lane][c] v[c] with v held one value per lane (R stride BS + 1),
-// four independent partial sums.
+// sum_c r[c] v[c] with v held one value per lane, four independent partial sums.
 template <typename V, int BS>
-__device__ __forceinline__ V row_times_lanes(const V *__restrict__ R, V v, int lane)
+__device__ __forceinline__ V row_times_lanes(const V (&r)[BS], V v)
 {
     V a[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int c = 0; c < BS; ++c) a[c & 3] += R[lane * (BS + 1) + c] * lane_bcast(v, c);
+    for (int c = 0; c < BS; ++c) a[c & 3] += r[c] * lane_bcast(v, c);
     return (a[0] + a[1]) + (a[2] + a[3]);
+}
+// row `lane` of an LDS matrix with stride BS + 1, into registers
+template <typename V, int BS>
+__device__ __forceinline__ void load_row(V (&r)[BS], const V *__restrict__ R, int lane)
+{
+#pragma unroll
+    for (int c = 0; c < BS; ++c) r[c] = R[lane * (BS + 1) + c];
 }
 
 // ---------------------------------------------------------------- lower
@@ -293,12 +299,17 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
             const int64_t src = perm ? (int64_t)perm[row] : row;
             z = b[src] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
         }
-        V w = row_times_lanes<V, BS>(Di, z, lane);
+        V rr[BS];
+        load_row<V, BS>(rr, Di, lane);
+        V w = row_times_lanes<V, BS>(rr, z);
         if (blk > 0) {
+            // the only work left after the predecessor publishes: one product
+            // with a row already in registers
+            load_row<V, BS>(rr, Dr, lane);
             lane_word<V> xp;
             xp.issue(tags, (int64_t)last * BS + lane, true);
             xp.settle(tags, (int64_t)last * BS + lane, true, epoch, &spins, flags);
-            w -= row_times_lanes<V, BS>(Dr, xp.value(), lane);
+            w -= row_times_lanes<V, BS>(rr, xp.value());
         }
         if (rv) {
             y[row] = w;
@@ -378,13 +389,16 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
     __syncthreads();
     if (wv == 0) {
         const V z = rv ? yin[row] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) : (V)0;
-        V w = row_times_lanes<V, BS>(Di, z, lane);
+        V rr[BS];
+        load_row<V, BS>(rr, Di, lane);
+        V w = row_times_lanes<V, BS>(rr, z);
         if (has_next) {
+            load_row<V, BS>(rr, Dr, lane);
             const bool valid = (int64_t)next * BS + lane < n;
             lane_word<V> xn;
             xn.issue(tags, (int64_t)next * BS + lane, valid);
             xn.settle(tags, (int64_t)next * BS + lane, valid, epoch, &spins, flags);
-            w -= row_times_lanes<V, BS>(Dr, valid ? xn.value() : (V)0, lane);
+            w -= row_times_lanes<V, BS>(rr, valid ? xn.value() : (V)0);
         }
         if (rv) {
             tagged<V>::put(tags, row, w, epoch);
