@@ -235,8 +235,11 @@ def test_mfma_rate_probe_does_its_work(env, prec):
 
 # ------------------------------------------------------------- solves
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
-@pytest.mark.parametrize("n", [100, 700])
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 100, 129, 700])
 def test_getrs_with_oracle_factors(env, prec, n):
+    """Single-block, exact-block and ragged sizes: each 64-row block inverts
+    its diagonal block and folds in its nearest predecessor through one
+    product, so the first, second and partial blocks are the edge cases."""
     n3p, torch = env
     A = random_matrix(n, 50 + n)
     b = np.random.default_rng(n).standard_normal(n)
@@ -251,6 +254,27 @@ def test_getrs_with_oracle_factors(env, prec, n):
     x = bt.double().cpu().numpy()
     tol = 1e-12 if prec == "fp64" else 2e-4
     assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < tol
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_getrs_many_blocks_with_oracle_factors(env, prec):
+    """33 row blocks with a ragged last one, diagonally dominant so that the
+    FP32 solve of the stored factors is compared at a conditioning-limited
+    tolerance rather than against a growth factor."""
+    n3p, torch = env
+    n = 2049
+    A = diag_dominant(n, 9)
+    b = np.random.default_rng(n).standard_normal(n)
+    LU, piv, info = O.getrf(A)
+    assert info == 0
+    dt = {"fp32": torch.float32, "fp16": torch.float16}[prec]
+    LUt = to_cm(torch, LU, dt)
+    LU_r = from_cm(LUt)
+    x_ref = O.getrs(LU_r, piv, b.astype(np.float32).astype(np.float64))
+    bt = torch.from_numpy(b).to("cuda", torch.float32)
+    n3p.getrs(LUt, torch.from_numpy(piv).cuda(), bt)
+    x = bt.double().cpu().numpy()
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-5
 
 
 @pytest.mark.parametrize("n", [1, 255, 1000, 2049])
