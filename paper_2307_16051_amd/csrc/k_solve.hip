@@ -607,7 +607,8 @@ hipError_t launch_krylov_update(int64_t n, const float *V, int64_t ldv, int k, c
 // the correction step of Algorithm 2.2 with the stored half-precision factors
 // promoted to FP32 as they are read (Section 2.3).  Blocked by 64: one wave
 // substitutes the diagonal block (a row per lane, readlane broadcasts), then
-// all waves update the remaining rows with coalesced column reads.
+// all waves update the remaining rows with coalesced column reads while the
+// next diagonal block's loads are in flight.
 template <typename T>
 __global__ __launch_bounds__(B_SOLVE_THREADS) void k_b_solve(const BDesc *__restrict__ d,
                                                              const BState *__restrict__ st,
@@ -623,15 +624,30 @@ __global__ __launch_bounds__(B_SOLVE_THREADS) void k_b_solve(const BDesc *__rest
     const T *__restrict__ A = (const T *)q.A;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nb = (int)(Np / 64);
+    // the next diagonal block is fetched into registers while the current
+    // block's update runs, and stored to Dg once the substitution is done
+    static_assert(NT * 4 == 64 * 64, "four diagonal entries per thread");
+    float pre[4];
+    auto fetch = [&](int64_t b0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = t + r * NT, i = e & 63, k = e >> 6;
+            pre[r] = to_f32(A[(b0 + i) + (b0 + k) * Np]);
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = t + r * NT, i = e & 63, k = e >> 6;
+            Dg[i][k] = pre[r];
+        }
+    };
     for (int64_t i = t; i < Np; i += NT) y[i] = q.r[i];
+    fetch(0);
+    put();
     __syncthreads();
     for (int blk = 0; blk < nb; ++blk) {  // forward, unit lower
         const int64_t b0 = (int64_t)blk * 64;
-        for (int e = t; e < 4096; e += NT) {
-            const int i = e & 63, k = e >> 6;
-            Dg[i][k] = to_f32(A[(b0 + i) + (b0 + k) * Np]);
-        }
-        __syncthreads();
         if (wave == 0) {
             float lr[64];
 #pragma unroll
@@ -642,6 +658,8 @@ __global__ __launch_bounds__(B_SOLVE_THREADS) void k_b_solve(const BDesc *__rest
             y[b0 + lane] = yi;
         }
         __syncthreads();
+        const bool more = blk + 1 < nb;
+        if (more) fetch(b0 + 64);
         for (int64_t i = b0 + 64 + t; i < Np; i += NT) {
             const T *__restrict__ col = A + i + b0 * Np;
             float acc = y[i];
@@ -649,15 +667,14 @@ __global__ __launch_bounds__(B_SOLVE_THREADS) void k_b_solve(const BDesc *__rest
             for (int k = 0; k < 64; ++k) acc -= to_f32(col[(int64_t)k * Np]) * y[b0 + k];
             y[i] = acc;
         }
+        if (more) put();
         __syncthreads();
     }
+    fetch((int64_t)(nb - 1) * 64);
+    put();
+    __syncthreads();
     for (int blk = nb - 1; blk >= 0; --blk) {  // backward, upper
         const int64_t b0 = (int64_t)blk * 64;
-        for (int e = t; e < 4096; e += NT) {
-            const int i = e & 63, k = e >> 6;
-            Dg[i][k] = to_f32(A[(b0 + i) + (b0 + k) * Np]);
-        }
-        __syncthreads();
         if (wave == 0) {
             float ur[64];
 #pragma unroll
@@ -672,6 +689,8 @@ __global__ __launch_bounds__(B_SOLVE_THREADS) void k_b_solve(const BDesc *__rest
             y[b0 + lane] = yi;
         }
         __syncthreads();
+        const bool more = blk > 0;
+        if (more) fetch(b0 - 64);
         for (int64_t i = t; i < b0; i += NT) {
             const T *__restrict__ col = A + i + b0 * Np;
             float acc = y[i];
@@ -679,6 +698,7 @@ __global__ __launch_bounds__(B_SOLVE_THREADS) void k_b_solve(const BDesc *__rest
             for (int k = 0; k < 64; ++k) acc -= to_f32(col[(int64_t)k * Np]) * y[b0 + k];
             y[i] = acc;
         }
+        if (more) put();
         __syncthreads();
     }
     for (int64_t i = t; i < Np; i += NT) {
