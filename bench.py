@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--solver", default="IR", choices=["IR", "GMRES_IR", "DIRECT"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-LU Newton comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-n", type=int, default=4096, help="oracle sample size")
+    ap.add_argument("--cpu-n", type=int, default=6144, help="oracle sample size (about 10-20 s of host work)")
     ap.add_argument("--no-mf", action="store_true",
                     help="skip the FFT / matrix-free comparison solve")
     ap.add_argument("--copy-calib", action="store_true",
