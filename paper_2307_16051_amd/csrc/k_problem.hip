@@ -110,6 +110,10 @@ __device__ __forceinline__ float block_max_256(float v, float *sh)
 // Fused H-equation Jacobian: one block per column j of the padded Np x Np
 // matrix.  Writes J (FP32, rows < n) and the factorisation copy Ah (type T,
 // Np rows, identity padding) with column scale colscale[j] (if non-null).
+// rowq (may be null): rowq[i] = (c/2N)(i + 1/2) / D_i^2, so that an entry
+// costs one product instead of a division (the FP64 value may differ from
+// the division form in the last bits; its FP32 rounding stays within the
+// FP32 rounding bound of the exact entry).
 template <typename T>
 __device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np, double c,
                                                const double *__restrict__ D,
@@ -117,7 +121,8 @@ __device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np,
                                                float *__restrict__ J, int64_t ldj,
                                                T *__restrict__ Ah, int64_t ldh,
                                                float *__restrict__ colscale, float target_log2,
-                                               int *flags, float *sh)
+                                               int *flags, float *sh,
+                                               const double *__restrict__ rowq = nullptr)
 {
     const int t = threadIdx.x;
     T *col = Ah ? Ah + j * ldh : nullptr;
@@ -130,10 +135,15 @@ __device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np,
     const double wgt = c / (2.0 * (double)n);
     float mx = 0.0f;
     bool bad = false;
-    for (int64_t i = t; i < n; i += 256) {
+    auto entry = [&](int64_t i) -> double {
+        const double hk = h ? h[i + j] : 1.0 / (double)(i + j + 1);
+        if (rowq) return (i == j ? 1.0 : 0.0) - rowq[i] * hk;
         const double di = D[i];
-        const double kij = wgt * ((double)i + 0.5) * (h ? h[i + j] : 1.0 / (double)(i + j + 1));
-        const double v = (i == j ? 1.0 : 0.0) - kij / (di * di);
+        const double kij = wgt * ((double)i + 0.5) * hk;
+        return (i == j ? 1.0 : 0.0) - kij / (di * di);
+    };
+    for (int64_t i = t; i < n; i += 256) {
+        const double v = entry(i);
         const float vf = (float)v;
         if (J) J[i + j * ldj] = vf;
         if (!isfinite(vf)) bad = true;
@@ -148,9 +158,7 @@ __device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np,
     }
     for (int64_t i = t; i < n; i += 256) {
         // recompute in the same order so the FP32 value is identical to J's
-        const double di = D[i];
-        const double kij = wgt * ((double)i + 0.5) * (h ? h[i + j] : 1.0 / (double)(i + j + 1));
-        const double v = (i == j ? 1.0 : 0.0) - kij / (di * di);
+        const double v = entry(i);
         if constexpr (std::is_same<T, double>::value) {
             col[i] = v;  // a double-precision factorisation takes the FP64 Jacobian itself
         } else {
@@ -170,10 +178,21 @@ __global__ __launch_bounds__(256) void k_heq_jac_round(int64_t n, int64_t Np, do
                                                        float *__restrict__ J, int64_t ldj,
                                                        T *__restrict__ Ah, int64_t ldh,
                                                        float *__restrict__ colscale,
-                                                       float target_log2, int *flags)
+                                                       float target_log2, int *flags,
+                                                       const double *__restrict__ rowq)
 {
     __shared__ float sh[256];
-    heq_jac_column<T>(blockIdx.x, n, Np, c, D, h, J, ldj, Ah, ldh, colscale, target_log2, flags, sh);
+    heq_jac_column<T>(blockIdx.x, n, Np, c, D, h, J, ldj, Ah, ldh, colscale, target_log2, flags, sh,
+                      rowq);
+}
+
+// rowq[i] = (c/2N)(i + 1/2) / D_i^2 (the Jacobian's row factor)
+__global__ void k_heq_rowq(int64_t n, double c, const double *__restrict__ D, double *__restrict__ rowq)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double di = D[i];
+    rowq[i] = (c / (2.0 * (double)n)) * ((double)i + 0.5) / (di * di);
 }
 
 // Generic J (FP32) -> Ah rounding with optional column scaling.
@@ -642,23 +661,25 @@ hipError_t launch_heq_residual(int64_t n, double c, const double *x, const doubl
 template <typename T>
 static hipError_t heq_jac_round_t(int64_t n, int64_t Np, double c, const double *D,
                                   const double *h, float *J, int64_t ldj, void *Ah, int64_t ldh,
-                                  float *colscale, float tl, int *flags, hipStream_t s)
+                                  float *colscale, float tl, int *flags, double *rowq, hipStream_t s)
 {
+    if (rowq)
+        hipLaunchKernelGGL(k_heq_rowq, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, c, D, rowq);
     hipLaunchKernelGGL(k_heq_jac_round<T>, dim3((unsigned)(Ah ? Np : n)), dim3(256), 0, s, n, Np,
-                       c, D, h, J, ldj, (T *)Ah, ldh, colscale, tl, flags);
+                       c, D, h, J, ldj, (T *)Ah, ldh, colscale, tl, flags, (const double *)rowq);
     return hipGetLastError();
 }
 
 // Fused H-equation Jacobian + rounding (declared in the host driver).
 hipError_t launch_heq_jac_round(int prec, int64_t n, int64_t Np, double c, const double *D,
                                 const double *h, float *J, int64_t ldj, void *Ah, int64_t ldh,
-                                float *colscale, float tl, int *flags, hipStream_t s)
+                                float *colscale, float tl, int *flags, double *rowq, hipStream_t s)
 {
     switch (prec) {
-    case N3P_FP16: return heq_jac_round_t<f16>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, s);
-    case N3P_BF16: return heq_jac_round_t<bf16>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, s);
-    case N3P_FP32: return heq_jac_round_t<float>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, s);
-    case N3P_FP64: return heq_jac_round_t<double>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, s);
+    case N3P_FP16: return heq_jac_round_t<f16>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, rowq, s);
+    case N3P_BF16: return heq_jac_round_t<bf16>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, rowq, s);
+    case N3P_FP32: return heq_jac_round_t<float>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, rowq, s);
+    case N3P_FP64: return heq_jac_round_t<double>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, nullptr, s);
     }
     return hipErrorInvalidValue;
 }
@@ -667,7 +688,8 @@ hipError_t launch_heq_jacobian(int64_t n, double c, const double *D, const doubl
                                int64_t ldj, hipStream_t s)
 {
     hipLaunchKernelGGL(k_heq_jac_round<float>, dim3((unsigned)n), dim3(256), 0, s, n, n, c, D, h, J,
-                       ldj, (float *)nullptr, (int64_t)0, (float *)nullptr, 0.0f, (int *)nullptr);
+                       ldj, (float *)nullptr, (int64_t)0, (float *)nullptr, 0.0f, (int *)nullptr,
+                       (const double *)nullptr);
     return hipGetLastError();
 }
 

@@ -713,8 +713,10 @@ static int build_jacobian(const n3p_problem *p, const SolveWs &w, const double *
     float *cs = scale ? w.colscale : nullptr;
     switch (p->kind) {
     case 0:
+        // the row factors go to the partial-sum scratch (n doubles), which
+        // nothing reads between the residual's norm and the linear solve
         HIPCHK(launch_heq_jac_round(w.prec, w.n, w.Np, p->c, w.D, w.h, w.J, w.n, w.f.A, w.Np, cs,
-                                    tl, w.f.flags, s));
+                                    tl, w.f.flags, w.part, s));
         return 0;
     case 1:
         if (w.prec == N3P_FP64) {  // the FP64 factorisation takes the unrounded Jacobian

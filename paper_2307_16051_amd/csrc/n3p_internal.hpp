@@ -121,9 +121,11 @@ hipError_t launch_heq_residual(int64_t n, double c, const double *x, const doubl
                                double *D, hipStream_t s);
 hipError_t launch_heq_jacobian(int64_t n, double c, const double *D, const double *h, float *J,
                                int64_t ldj, hipStream_t s);
+// rowq: optional n-double scratch for the Jacobian's row factors (ignored
+// for the FP64 factorisation, which keeps the division form)
 hipError_t launch_heq_jac_round(int prec, int64_t n, int64_t Np, double c, const double *D,
                                 const double *h, float *J, int64_t ldj, void *Ah, int64_t ldh,
-                                float *colscale, float tl, int *flags, hipStream_t s);
+                                float *colscale, float tl, int *flags, double *rowq, hipStream_t s);
 hipError_t launch_dense_tanh_residual(int64_t n, const double *A, int64_t lda, const double *b,
                                       const double *x, double *F, double *part, hipStream_t s);
 hipError_t launch_dense_tanh_jacobian(int64_t n, const double *A, int64_t lda, const double *x,
