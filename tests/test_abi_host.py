@@ -7,6 +7,7 @@ workspace sizing) are exercised directly.
 import ctypes
 import os
 import re
+import sys
 
 import pytest
 
@@ -100,3 +101,29 @@ def test_mfma_rate_probe_rejects_bad_arguments(lib):
     assert lib.n3p_mfma_rate_probe(FP16, 1, (1 << 20) + 1, buf, ctypes.byref(fl), None) == -1
     assert lib.n3p_mfma_rate_probe(FP16, 1, 1, None, ctypes.byref(fl), None) == -1
 
+
+
+def test_traffic_counters_are_keyed_to_kernels_and_schedule(tmp_path):
+    """The stored HBM-traffic figure is reported only for the factorisation
+    it was measured on: its key changes with the kernel source and with the
+    launch schedule, and not with unrelated host code."""
+    import shutil
+    sys.path.insert(0, ROOT)
+    import bench
+    csrc = os.path.join(ROOT, "paper_2307_16051_amd", "csrc")
+    root2 = tmp_path / "r"
+    dst = root2 / "paper_2307_16051_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for f in ("k_getrf.hip", "n3p_api.cpp"):
+        shutil.copy(os.path.join(csrc, f), dst / f)
+    base = bench.factor_source_sha(str(root2))
+    assert base == bench.factor_source_sha(ROOT)
+    api = (dst / "n3p_api.cpp").read_text()
+    (dst / "n3p_api.cpp").write_text(api + "\n// unrelated host code\n")
+    assert bench.factor_source_sha(str(root2)) == base
+    i = api.index("int getrf_spec(")
+    (dst / "n3p_api.cpp").write_text(api[:i] + api[i:].replace("NB_MID", "NB_OUT", 1))
+    assert bench.factor_source_sha(str(root2)) != base
+    (dst / "n3p_api.cpp").write_text(api)
+    (dst / "k_getrf.hip").write_text((dst / "k_getrf.hip").read_text() + "\n")
+    assert bench.factor_source_sha(str(root2)) != base
