@@ -91,9 +91,11 @@ __device__ __forceinline__ void leaf_body(int bid, int64_t Np, int64_t c0, T *__
 {
     typedef typename compute_of<T>::type CT;
     constexpr int L = NB_LEAF;
-    constexpr int LP = L + 4;
+    constexpr int LP = L + 5;  // staging row stride: column chunks conflict-free, octet accesses 2-way
     constexpr int NT = LEAF_THREADS;
-    __shared__ __attribute__((aligned(16))) CT Dm[L][LP];       // diagonal block
+    // diagonal block; odd row stride, so the column accesses (lane = row)
+    // of the strips hit 64 different banks
+    __shared__ __attribute__((aligned(16))) CT Dm[L][L + 1];
     // Per column group kc of the tile solves: Ui[kc][kq][g][c] =
     // U[8kc+kq][8(kc+c)+g] and Li[kc][kq][g][u] = L[8(kc+u)+g][8kc+kq] where
     // kc + c <= 7 and that index exceeds the row (column) 8kc+kq, else 0 -- so
