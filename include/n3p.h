@@ -220,6 +220,12 @@ N3P_API size_t n3p_getrf_workspace_size(int64_t n, int prec);
  * the lowest row.  *info (host): 0, or k+1 if U(k,k) is exactly zero, or -1
  * if the factors are not finite.  Synchronises the stream.  The input is
  * factored as given (no scaling); n3p_solve adds the column scaling.
+ * Size limit of the pivoting path: a matrix that partial pivoting would
+ * factor with row interchanges (rather than with the diagonal pivots the
+ * factorisation tries first) is factored by the pivoting path, which holds
+ * one row per thread in at most 128 resident workgroups of 256 threads, so it
+ * takes n <= 32768; a larger matrix that needs interchanges returns
+ * N3P_E_INVALID (n3p_solve likewise).
  */
 N3P_API int n3p_getrf(int prec, int64_t n, void *A, int64_t lda, int32_t *ipiv, int *info,
                       void *ws, size_t ws_bytes, void *stream);
@@ -310,7 +316,7 @@ N3P_API int n3p_heq_jv(int64_t n, double c, const double *D, const float *v, flo
  * Algorithm 2.1 together: one engine step is one Newton iteration for every
  * admitted request (Jacobian stored FP32 and rounded to lu_prec, the
  * no-interchange half-precision LU verified against partial pivoting, IR
- * sweeps of Algorithm 2.2 with the Section 3.1 policy, FP64 update and
+ * sweeps of the IR algorithm of Section 2.2 with the Section 3.1 policy, FP64 update and
  * residual), as batched kernels over a device table of slots, replayed from
  * captured HIP graphs.  Requests join between steps as slots and pool memory
  * free up and leave when their stopping test passes.  A request's arithmetic

@@ -168,6 +168,17 @@ def perm_from_ipiv(ipiv: np.ndarray) -> np.ndarray:
     return p
 
 
+def gemv(A: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y = A x in FP64 (the product inside the refinement residual r = b - A u
+    of the IR algorithm, Section 2.2)."""
+    A = np.asfortranarray(_f64(A))
+    n = A.shape[0]
+    x = _f64(x)
+    y = np.zeros(n)
+    _load().orc_gemv(n, _p(A), n, _p(x), _p(y))
+    return y
+
+
 def nrm2(v: np.ndarray) -> float:
     v = _f64(v)
     return float(_load().orc_nrm2(v.size, _p(v)))

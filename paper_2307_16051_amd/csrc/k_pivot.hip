@@ -30,8 +30,10 @@ namespace n3p {
 // workgroup publishes column k + 2 only after every workgroup has published
 // column k + 1, which each does only after it has finished reading column k.
 //
-// P <= 128 workgroups of 512 threads (1024 rows each, 512 for FP64) fill one
-// CU each on an otherwise idle device, so all are resident together.  Every wait is bounded regardless: an
+// P <= PIVOT_MAX_WG workgroups of 256 threads, one row per thread (256 rows
+// per workgroup), fill one CU each on an otherwise idle device, so all are
+// resident together; this bounds the pivoting path to Np <= 128 * 256 = 32768
+// rows (the host checks it before the first launch).  Every wait is bounded regardless: an
 // expired wait raises FLAG_TIMEOUT and the wavefront stops waiting, so the grid
 // always drains (the factors are then invalid and the caller reports the
 // timeout).
@@ -40,9 +42,9 @@ namespace n3p {
 // slots after each group, so the current group's columns always sit in slots
 // 0..7 (compile-time register indices): in group g, slot s holds panel column
 // (s + 8 g) mod 64 and slots >= 64 - 8 g hold finished columns.
-constexpr int PC_SPIN_LIMIT = 1 << 20;
+constexpr int PC_SPIN_LIMIT = 1 << 20;         // polls of ~1 us: a wait that long has failed
 constexpr int PC_LIST_INTS = 1 + 4 * NB_LEAF;  // count + 128 (dest, src) pairs
-constexpr int PC_NLIST = NB_OUT / NB_LEAF;     // one list per leaf of an outer block  // polls of ~1 us: a wait that long has failed
+constexpr int PC_NLIST = NB_OUT / NB_LEAF;     // one list per leaf of an outer block
 
 template <typename CT> struct pc_cfg;
 // rows per thread, words per value, threads per workgroup
@@ -641,7 +643,7 @@ hipError_t launch_pivot_coop(int prec, int64_t Np, int64_t c0, int64_t k0, void 
 {
     const int64_t rw = pc_rows_per_wg(prec), m = Np - c0;
     const int64_t P = (m + rw - 1) / rw, pmax = pc_pmax(prec, Np);
-    if (m < NB_LEAF || m % NB_LEAF || P > 128) return hipErrorInvalidValue;
+    if (m < NB_LEAF || m % NB_LEAF || P > PIVOT_MAX_WG) return hipErrorInvalidValue;
     switch (prec) {
     case N3P_FP16: return pivot_coop_t<f16, float>(Np, c0, k0, A, lda, ipiv, LT, xch, (int)pmax, (int)P, flags, s);
     case N3P_BF16: return pivot_coop_t<bf16, float>(Np, c0, k0, A, lda, ipiv, LT, xch, (int)pmax, (int)P, flags, s);

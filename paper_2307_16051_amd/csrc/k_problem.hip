@@ -559,7 +559,7 @@ __global__ __launch_bounds__(256) void k_b_jac(const BDesc *__restrict__ d,
 }
 
 // After the factorisation: unit right-hand side b = -F/||F|| (eq. (2.17)),
-// u = 0, r = b, and the IR state (Algorithm 2.2).  A slot whose matrix needs
+// u = 0, r = b, and the IR state (the IR algorithm of Section 2.2).  A slot whose matrix needs
 // row interchanges, or whose factors are not finite, ends here.
 __global__ __launch_bounds__(256) void k_b_ir_init(const BDesc *__restrict__ d,
                                                    BState *__restrict__ st, int nslots, BParams p)

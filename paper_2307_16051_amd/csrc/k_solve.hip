@@ -604,7 +604,7 @@ hipError_t launch_krylov_update(int64_t n, const float *V, int64_t ldv, int k, c
 // ====================================================== batched engine kernels
 // One workgroup per slot (N <= B_MAX_NP): y = L^{-1} r (unit lower), then
 // z = U^{-1} y, d = S z (S the FP16 column scale), and uprev = u, u += d:
-// the correction step of Algorithm 2.2 with the stored half-precision factors
+// the correction step of the IR algorithm of Section 2.2 with the stored half-precision factors
 // promoted to FP32 as they are read (Section 2.3).  Blocked by 64: one wave
 // substitutes the diagonal block (a row per lane, readlane broadcasts), then
 // all waves update the remaining rows with coalesced column reads while the

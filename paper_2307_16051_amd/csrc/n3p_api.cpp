@@ -243,6 +243,14 @@ int getrf_run(const FactorWs &f, hipStream_t s, Refill refill, FactorResult *res
     CHK(read_flags(f, s, h));
     res->pivoted = false;
     if (h[FLAG_FAIL]) {
+        // the pivoting path holds one row per thread in at most PIVOT_MAX_WG
+        // resident workgroups
+        if (f.Np > PIVOT_MAX_NP) {
+            if (std::getenv("N3P_DEBUG"))
+                std::fprintf(stderr, "n3p: the matrix needs row interchanges and the pivoting "
+                                     "path supports n <= %lld\n", (long long)PIVOT_MAX_NP);
+            return N3P_E_INVALID;
+        }
         CHK(refill());
         HIPCHK(launch_fill_i32(f.flags, 0, NFLAGS, s));
         CHK(getrf_pivot(f, s));
@@ -774,10 +782,19 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
         }
         return 0;
     };
-    hipEvent_t e_all0 = nullptr, e_all1 = nullptr;
-    HIPCHK(hipEventCreate(&e_all0));
-    HIPCHK(hipEventCreate(&e_all1));
-    HIPCHK(hipEventRecord(e_all0, s));
+    // the two events bracketing the solve; the guard destroys them on every
+    // return path, early error returns included
+    struct EventPair {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~EventPair()
+        {
+            if (a) hipEventDestroy(a);
+            if (b) hipEventDestroy(b);
+        }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    HIPCHK(hipEventRecord(ev.a, s));
 
     Epoch epoch;
     HIPCHK(launch_fill_i32(w.sync, 0, (int64_t)trsv_sync_ints(w.Np), s));
@@ -945,12 +962,10 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
         if (!std::isfinite(fn)) { status = N3P_E_NONFINITE; break; }
     }
     if (status == N3P_OK && fn > tau) status = N3P_NOT_CONVERGED;
-    HIPCHK(hipEventRecord(e_all1, s));
-    HIPCHK(hipEventSynchronize(e_all1));
+    HIPCHK(hipEventRecord(ev.b, s));
+    HIPCHK(hipEventSynchronize(ev.b));
     float tot = 0;
-    HIPCHK(hipEventElapsedTime(&tot, e_all0, e_all1));
-    hipEventDestroy(e_all0);
-    hipEventDestroy(e_all1);
+    HIPCHK(hipEventElapsedTime(&tot, ev.a, ev.b));
     if (tslot > 0) {
         std::vector<uint64_t> st((size_t)tslot);
         HIPCHK(hipMemcpyAsync(st.data(), w.stamps, (size_t)tslot * 8, hipMemcpyDeviceToHost, s));

@@ -3,7 +3,7 @@
 // Many independent H-equation solves (eq. (3.2)) advance through Algorithm 2.1
 // together: one engine step performs one Newton iteration for every admitted
 // request -- Jacobian stored FP32 and rounded to half precision, the
-// half-precision LU, IR sweeps (Algorithm 2.2 with the Section 3.1 policy),
+// half-precision LU, IR sweeps (the IR algorithm of Section 2.2 with the Section 3.1 policy),
 // the FP64 update and residual -- as a fixed sequence of batched kernels that
 // walk a device table of slots.  Requests join at step boundaries as slots and
 // pool memory free up, and leave when their stopping test passes, so work of

@@ -26,6 +26,10 @@ constexpr int NB_PAD = 512;   // factorisation sizes are padded to a multiple of
 constexpr int NB_LEAF = 64;   // leaf panel width
 constexpr int NB_MID = 256;   // middle level: leaves' rank-64 updates stay inside it
 constexpr int TRSV_BS = 64;   // row block of the triangular solves
+// the pivoting path keeps one row per thread in at most PIVOT_MAX_WG
+// workgroups of 256 threads, all resident at once
+constexpr int PIVOT_MAX_WG = 128;
+constexpr int64_t PIVOT_MAX_NP = (int64_t)PIVOT_MAX_WG * 256;
 constexpr int FLAG_FAIL = 0, FLAG_NONFINITE = 1, FLAG_ZEROPIV = 2, FLAG_TIMEOUT = 3;
 constexpr int NFLAGS = 16;
 

@@ -284,7 +284,7 @@ def test_gemv_resid_matches_fp64_definition(env, n):
     A = rng.standard_normal((n, n)).astype(np.float32)
     u = rng.standard_normal(n).astype(np.float32)
     b = rng.standard_normal(n).astype(np.float32)
-    r_ref = b.astype(np.float64) - A.astype(np.float64) @ u.astype(np.float64)
+    r_ref = b.astype(np.float64) - O.gemv(A, u)
     r = n3p.gemv_resid(to_cm(torch, A, torch.float32), torch.from_numpy(u).cuda(),
                        torch.from_numpy(b).cuda()).cpu().numpy().astype(np.float64)
     scale = np.abs(b) + np.abs(A.astype(np.float64)) @ np.abs(u.astype(np.float64))

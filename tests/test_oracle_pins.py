@@ -169,6 +169,27 @@ def test_dense_tanh_jacobian_vs_central_differences():
     assert np.abs(J - Jfd).max() / np.abs(J).max() < 1e-7
 
 
+def test_gemv_hand_product_and_closed_forms():
+    """The oracle's matrix-vector product (the refinement residual's A u):
+    a product evaluated by hand, a permutation matrix (y is x permuted) and a
+    rank-one matrix (y = a * (b . x)), which catch a transposed operand, a
+    dropped term or a wrong index."""
+    A = np.array([[1.0, -2.0, 0.5], [3.0, 0.0, -1.0], [2.0, 4.0, 1.0]])
+    x = np.array([2.0, -1.0, 4.0])
+    # rows: 2 + 2 + 2 = 6;  6 + 0 - 4 = 2;  4 - 4 + 4 = 4
+    np.testing.assert_array_equal(O.gemv(A, x), [6.0, 2.0, 4.0])
+    n = 37
+    rng = np.random.default_rng(3)
+    p = rng.permutation(n)
+    P = np.zeros((n, n))
+    P[np.arange(n), p] = 1.0
+    x = rng.standard_normal(n)
+    np.testing.assert_array_equal(O.gemv(P, x), x[p])
+    a, b = rng.standard_normal(n), rng.standard_normal(n)
+    y = O.gemv(np.outer(a, b), x)
+    np.testing.assert_allclose(y, a * float(b @ x), rtol=1e-13, atol=1e-13 * np.abs(a).max())
+
+
 def test_getrf_hand_worked_3x3():
     """Partial pivoting on a 3x3 example eliminated by hand."""
     A = np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0], [7.0, 8.0, 10.0]])
