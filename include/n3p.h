@@ -257,6 +257,25 @@ N3P_API int n3p_mfma_rate_probe(int prec, int blocks, int iters, float *out, dou
 N3P_API int n3p_gemv_resid_f32(int64_t n, const float *A, int64_t lda, const float *u,
                                const float *b, float *r, void *ws, size_t ws_bytes, void *stream);
 
+/* r = b - A u exactly as n3p_gemv_resid_f32 (same kernels, same FP64
+ * partial sums in the same order, so bit-identical results), for callers that
+ * cannot allocate device memory: code being captured into a HIP graph,
+ * serving loops that must not call hipMalloc, harnesses that forbid it.  No
+ * workspace is passed: the FP64 partial sums (n * ceil(n/256) doubles) live
+ * in a scratch array compiled into the library, N3P_GEMV_NOALLOC_MAX_N *
+ * (N3P_GEMV_NOALLOC_MAX_N / 256) doubles = 8 MiB, one copy per device, held
+ * until the process ends.  Its device address is looked up once per device,
+ * on the first call made with that device current.  n <= 16384
+ * (N3P_GEMV_NOALLOC_MAX_N); a larger n returns N3P_E_INVALID before any
+ * device work.  Every partial sum is written before it is read, so no call
+ * depends on what an earlier call left in the scratch; but all calls on one
+ * device share it, so calls that overlap in time on one device (different
+ * streams, threads or processes without ordering) race and must be
+ * serialised by the caller.  Asynchronous on `stream`. */
+#define N3P_GEMV_NOALLOC_MAX_N 16384
+N3P_API int n3p_gemv_resid_f32_noalloc(int64_t n, const float *A, int64_t lda, const float *u,
+                                       const float *b, float *r, void *stream);
+
 /* H-equation residual, eq. (3.2): F (and D_i = the bracket) in FP64, device
  * arrays of length n (D may be NULL).  Asynchronous. */
 N3P_API int n3p_heq_residual(int64_t n, double c, const double *x, double *F, double *D,

@@ -140,11 +140,12 @@ ORC_API double orc_nrm2(int64_t n, const double *v)
     return sqrt(s);
 }
 
-/* y = A x for column-major A (n-by-n). */
-ORC_API int orc_gemv(int64_t n, const double *A, int64_t lda, const double *x, double *y)
+/* y = A x for column-major A (m-by-n): each y_i summed over j in order. */
+ORC_API int orc_gemv(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
+                     double *y)
 {
-#pragma omp parallel for schedule(static) if (n >= 512)
-    for (int64_t i = 0; i < n; ++i) {
+#pragma omp parallel for schedule(static) if (m >= 512)
+    for (int64_t i = 0; i < m; ++i) {
         double s = 0.0;
         for (int64_t j = 0; j < n; ++j) s += A[i + j * lda] * x[j];
         y[i] = s;

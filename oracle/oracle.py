@@ -53,7 +53,7 @@ def _load():
     lib.orc_dense_tanh_jacobian.argtypes = [i64, _dp, i64, _dp, _dp, i64]
     lib.orc_nrm2.argtypes = [i64, _dp]
     lib.orc_nrm2.restype = f64
-    lib.orc_gemv.argtypes = [i64, _dp, i64, _dp, _dp]
+    lib.orc_gemv.argtypes = [i64, i64, _dp, i64, _dp, _dp]
     lib.orc_getrf.argtypes = [i64, _dp, i64, _ip]
     lib.orc_getrs.argtypes = [i64, _dp, i64, _ip, _dp]
     lib.orc_newton_heq.argtypes = [i64, f64, _dp, f64, f64, i32, i32, _dp,
@@ -169,13 +169,14 @@ def perm_from_ipiv(ipiv: np.ndarray) -> np.ndarray:
 
 
 def gemv(A: np.ndarray, x: np.ndarray) -> np.ndarray:
-    """y = A x in FP64 (the product inside the refinement residual r = b - A u
-    of the IR algorithm, Section 2.2)."""
+    """y = A x in FP64 for an m x n matrix (the product inside the refinement
+    residual r = b - A u of the IR algorithm, Section 2.2)."""
     A = np.asfortranarray(_f64(A))
-    n = A.shape[0]
+    m, n = A.shape
     x = _f64(x)
-    y = np.zeros(n)
-    _load().orc_gemv(n, _p(A), n, _p(x), _p(y))
+    assert x.size == n
+    y = np.zeros(m)
+    _load().orc_gemv(m, n, _p(A), m, _p(x), _p(y))
     return y
 
 

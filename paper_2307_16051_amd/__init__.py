@@ -14,7 +14,7 @@ from ._binding import (  # noqa: F401
     FP16, BF16, FP32, FP64, IR, GMRES_IR, DIRECT, SCALE_AUTO, SCALE_NONE,
     Options, Report, N3PError, lib, lib_path, status_str, version,
     workspace_size, solve_heq, solve_dense_tanh, solve,
-    getrf, getrs, gemv_resid, heq_residual, heq_jacobian, ir, gmres_ir,
+    getrf, getrs, gemv_resid, gemv_resid_noalloc, GEMV_NOALLOC_MAX_N, heq_residual, heq_jacobian, ir, gmres_ir,
     EngineConfig, ServeStats, Engine, serve, engine_request_bytes, engine_fixed_bytes,
     PHASE_FREE, PHASE_ADMITTED, PHASE_RUNNING, PHASE_DONE, heq_residual_fft, heq_jv,
     mfma_rate_probe,

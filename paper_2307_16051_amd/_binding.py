@@ -136,8 +136,10 @@ def _setup():
     L.n3p_gmres_ir.argtypes = [_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _f64, _int,
                                _int, _f64, _ip, _ip, _ip, _dp, _vp, ctypes.c_size_t, _vp]
     L.n3p_mfma_rate_probe.argtypes = [_int, _int, _int, _vp, _dp, _vp]
+    L.n3p_gemv_resid_f32_noalloc.argtypes = [_i64, _vp, _i64, _vp, _vp, _vp, _vp]
     for name in ("n3p_problem_heq", "n3p_problem_dense_tanh", "n3p_problem_callbacks",
-                 "n3p_solve", "n3p_getrf", "n3p_getrs", "n3p_gemv_resid_f32", "n3p_heq_residual",
+                 "n3p_solve", "n3p_getrf", "n3p_getrs", "n3p_gemv_resid_f32",
+                 "n3p_gemv_resid_f32_noalloc", "n3p_heq_residual",
                  "n3p_heq_jacobian", "n3p_ir", "n3p_gmres_ir", "n3p_mfma_rate_probe"):
         getattr(L, name).restype = _int
 
@@ -275,6 +277,21 @@ def gemv_resid(A: torch.Tensor, u: torch.Tensor, b: torch.Tensor) -> torch.Tenso
     ws = _ws(8 * max(256, n * ((n + 255) // 256)), A.device)
     _check(lib.n3p_gemv_resid_f32(n, _ptr(A), n, _ptr(u), _ptr(b), _ptr(r), _ptr(ws), ws.numel(),
                                   _stream()), "n3p_gemv_resid_f32")
+    return r
+
+
+GEMV_NOALLOC_MAX_N = 16384  # N3P_GEMV_NOALLOC_MAX_N
+
+
+def gemv_resid_noalloc(A: torch.Tensor, u: torch.Tensor, b: torch.Tensor,
+                       r: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """r = b - A u through n3p_gemv_resid_f32_noalloc (no workspace; the
+    library's fixed scratch, n <= GEMV_NOALLOC_MAX_N)."""
+    n = _colmajor(A)
+    if r is None:
+        r = torch.empty_like(b)
+    _check(lib.n3p_gemv_resid_f32_noalloc(n, _ptr(A), n, _ptr(u), _ptr(b), _ptr(r), _stream()),
+           "n3p_gemv_resid_f32_noalloc")
     return r
 
 

@@ -14,6 +14,7 @@
 // the fly, Section 2.3).  Every wait is bounded; an expired wait raises
 // FLAG_TIMEOUT and the block proceeds so that the grid always drains.
 #include <algorithm>
+#include <mutex>
 
 #include "n3p_internal.hpp"
 
@@ -529,6 +530,51 @@ hipError_t launch_gemv_f32(int64_t n, const float *A, int64_t lda, const float *
                            double *part, hipStream_t s)
 {
     return launch_gemv_resid(n, A, lda, v, nullptr, y, part, s);
+}
+
+// ------------------------------------------------ allocation-free matvec
+// Fixed scratch for the allocation-free form of r = b - A u: the FP64
+// partial sums of one call, n * ceil(n / MV_CH) doubles for n <= GEMV_NOALLOC_MAX_N
+// (8 MiB).  Each device holds its own copy at its own address until the
+// process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory, so it is never passed to a kernel: the device address is looked up
+// with hipGetSymbolAddress once per device (with that device current) and
+// that pointer is what the kernels receive.
+constexpr int64_t GEMV_NOALLOC_MAX_N = N3P_GEMV_NOALLOC_MAX_N;
+constexpr size_t GEMV_NOALLOC_DOUBLES = (size_t)GEMV_NOALLOC_MAX_N * (GEMV_NOALLOC_MAX_N / MV_CH);
+static_assert(GEMV_NOALLOC_MAX_N % MV_CH == 0, "scratch sized for whole column chunks");
+static __device__ __align__(256) double scratch[GEMV_NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[NOALLOC_MAX_DEVICES];
+
+static hipError_t noalloc_scratch(double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_gemv_resid_noalloc(int64_t n, const float *A, int64_t lda, const float *u,
+                                     const float *b, float *r, hipStream_t s)
+{
+    if (n < 1 || n > GEMV_NOALLOC_MAX_N) return hipErrorInvalidValue;
+    double *part = nullptr;
+    const hipError_t e = noalloc_scratch(&part);
+    if (e != hipSuccess) return e;
+    return launch_gemv_resid(n, A, lda, u, b, r, part, s);
 }
 
 // ----------------------------------------------------------------- GMRES

@@ -1277,6 +1277,15 @@ N3P_API int n3p_gemv_resid_f32(int64_t n, const float *A, int64_t lda, const flo
     return N3P_OK;
 }
 
+N3P_API int n3p_gemv_resid_f32_noalloc(int64_t n, const float *A, int64_t lda, const float *u,
+                                       const float *b, float *r, void *stream)
+{
+    if (n < 1 || n > N3P_GEMV_NOALLOC_MAX_N || !A || lda < n || !u || !b || !r)
+        return N3P_E_INVALID;
+    HIPCHK(launch_gemv_resid_noalloc(n, A, lda, u, b, r, (hipStream_t)stream));
+    return N3P_OK;
+}
+
 N3P_API int n3p_mfma_rate_probe(int prec, int blocks, int iters, float *out, double *flops,
                                 void *stream)
 {

@@ -220,6 +220,10 @@ hipError_t launch_trsv_upper_f64(int64_t n, const double *LU, int64_t lda, const
                                  double *x, int *sync, uint32_t epoch, int *flags, hipStream_t s);
 hipError_t launch_gemv_resid(int64_t n, const float *A, int64_t lda, const float *u,
                              const float *b, float *r, double *part, hipStream_t s);
+// the same r = b - A u with the partial sums in the library's fixed scratch
+// (n <= N3P_GEMV_NOALLOC_MAX_N); allocates nothing
+hipError_t launch_gemv_resid_noalloc(int64_t n, const float *A, int64_t lda, const float *u,
+                                     const float *b, float *r, hipStream_t s);
 // y = A v (FP32 out) for GMRES
 hipError_t launch_gemv_f32(int64_t n, const float *A, int64_t lda, const float *v, float *y,
                            double *part, hipStream_t s);

@@ -102,6 +102,21 @@ def test_mfma_rate_probe_rejects_bad_arguments(lib):
     assert lib.n3p_mfma_rate_probe(FP16, 1, 1, None, ctypes.byref(fl), None) == -1
 
 
+def test_gemv_noalloc_rejects_bad_arguments(lib):
+    """The allocation-free matvec validates sizes and pointers before it
+    touches a device (no GPU here): n beyond the fixed scratch, n < 1, a
+    short leading dimension, a null pointer."""
+    import ctypes
+    p = ctypes.c_void_p(1)  # never dereferenced: validation fails first
+    nmax = 16384
+    f = lib.n3p_gemv_resid_f32_noalloc
+    f.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert f(nmax + 1, p, nmax + 1, p, p, p, None) == -1
+    assert f(0, p, 1, p, p, p, None) == -1
+    assert f(100, p, 99, p, p, p, None) == -1
+    assert f(100, p, 100, None, p, p, None) == -1
+
 
 def test_traffic_counters_are_keyed_to_kernels_and_schedule(tmp_path):
     """The stored HBM-traffic figure is reported only for the factorisation

@@ -188,6 +188,8 @@ def test_gemv_hand_product_and_closed_forms():
     a, b = rng.standard_normal(n), rng.standard_normal(n)
     y = O.gemv(np.outer(a, b), x)
     np.testing.assert_allclose(y, a * float(b @ x), rtol=1e-13, atol=1e-13 * np.abs(a).max())
+    # rectangular: the leading rows of the hand example
+    np.testing.assert_array_equal(O.gemv(A[:2, :], np.array([2.0, -1.0, 4.0])), [6.0, 2.0])
 
 
 def test_getrf_hand_worked_3x3():
