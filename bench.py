@@ -279,14 +279,17 @@ def fp64_baseline(n3p, torch, dev, n, c, x, getrf_flops, ms_per, out):
 
 def factor_source_sha(root=ROOT):
     """SHA-256 over what decides the factorisation's memory traffic: the
-    kernel source (k_getrf.hip) and the launch schedule (getrf_spec)."""
+    kernel sources (k_getrf.hip, k_panel.hip) and the launch schedules
+    (getrf_spec, getrf_spec_top)."""
     import hashlib
     csrc = os.path.join(root, "paper_2307_16051_amd", "csrc")
     api = open(os.path.join(csrc, "n3p_api.cpp")).read()
-    i = api.index("int getrf_spec(")
-    sched = api[i:api.index("\n}\n", i)]
-    h = hashlib.sha256(open(os.path.join(csrc, "k_getrf.hip"), "rb").read())
-    h.update(sched.encode())
+    h = hashlib.sha256()
+    for src in ("k_getrf.hip", "k_panel.hip"):
+        h.update(open(os.path.join(csrc, src), "rb").read())
+    for fn in ("int getrf_spec(", "int getrf_spec_top("):
+        i = api.index(fn)
+        h.update(api[i:api.index("\n}\n", i)].encode())
     return h.hexdigest()
 
 

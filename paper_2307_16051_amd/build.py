@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libn3p.so")
-SOURCES = ["k_problem.hip", "k_getrf.hip", "k_pivot.hip", "k_solve.hip", "k_fft.hip", "k_bench.hip", "n3p_api.cpp", "n3p_batch.cpp"]
+SOURCES = ["k_problem.hip", "k_getrf.hip", "k_panel.hip", "k_pivot.hip", "k_solve.hip", "k_fft.hip", "k_bench.hip", "n3p_api.cpp", "n3p_batch.cpp"]
 ARCH = "gfx950"
 
 

@@ -74,19 +74,29 @@ struct FactorWs {
     int32_t *ipiv = nullptr;  // Np
     int32_t *perm = nullptr;  // Np (device), valid if pivoted
     int *flags = nullptr;     // NFLAGS
+    uint64_t *pub = nullptr;  // FP16/BF16: publication words of the diagonal-square kernel
+    float *inv = nullptr;     // FP16/BF16: the leaves' triangular inverses
 };
+
+bool top_path(int prec) { return prec == N3P_FP16 || prec == N3P_BF16; }
 
 size_t factor_bytes(int prec, int64_t Np, Bump &b, FactorWs *f, char *base)
 {
     const size_t es = elem_size(prec);
     size_t oA = b.take((size_t)Np * Np * es);
-    size_t oLT = b.take((size_t)Np * NB_OUT * es);
+    // the diagonal-square path double-buffers LT by block parity (the next
+    // block's square is factored while this block's update still reads LT)
+    size_t oLT = b.take((size_t)Np * NB_OUT * es * (top_path(prec) ? 2 : 1));
     size_t oDG = b.take((size_t)2 * NB_LEAF * NB_LEAF * es);
     size_t oS = b.take(pivot_xch_bytes(prec, Np));
     size_t oI = b.take((size_t)Np * 4);
     size_t oP = b.take((size_t)Np * 4);
     size_t oF = b.take((size_t)NFLAGS * 4);
+    size_t oPub = top_path(prec) ? b.take(top_pub_words() * 8) : 0;
+    size_t oInv = top_path(prec) ? b.take(top_inv_floats() * 4) : 0;
     if (f && base) {
+        f->pub = top_path(prec) ? (uint64_t *)(base + oPub) : nullptr;
+        f->inv = top_path(prec) ? (float *)(base + oInv) : nullptr;
         f->prec = prec;
         f->Np = Np;
         f->A = base + oA;
@@ -176,6 +186,50 @@ int getrf_spec(const FactorWs &f, hipStream_t s)
     return 0;
 }
 
+// No-interchange attempt for FP16 / BF16 (verified against the
+// partial-pivoting rule), one outer block of up to NB_OUT columns at a time,
+// with look-ahead: block j's L below its square and U right of it (k_trsm),
+// the update of block j + 1's columns, then block j + 1's square factored
+// in the same launch as the rest of block j's update.  LT alternates between
+// two buffers by block parity.  Publication tags are unique within a
+// factorisation (the area is cleared once at its start).
+int getrf_spec_top(const FactorWs &f, hipStream_t s)
+{
+    const int prec = f.prec;
+    const int64_t Np = f.Np, lda = Np;
+    const size_t es = elem_size(prec);
+    char *A = (char *)f.A;
+    char *LTb[2] = {(char *)f.LT, (char *)f.LT + (size_t)Np * NB_OUT * es};
+    auto at = [&](int64_t i, int64_t j) { return (void *)(A + ((size_t)i + (size_t)j * lda) * es); };
+    HIPCHK(launch_fill_i32((int *)f.pub, 0, (int64_t)(top_pub_words() * 2), s));
+    uint32_t tag0 = 1;
+    HIPCHK(launch_top(prec, 0, (int)std::min<int64_t>(NB_OUT, Np), f.A, lda, LTb[0], f.pub, f.inv,
+                      f.flags, tag0, s));
+    for (int64_t j = 0;; ++j) {
+        const int64_t k0 = j * NB_OUT;
+        const int W = (int)std::min<int64_t>(NB_OUT, Np - k0);
+        const int64_t kend = k0 + W;
+        if (kend >= Np) break;
+        char *LTj = LTb[j & 1];
+        const void *Lbelow = LTj + (size_t)kend * NB_OUT * es;
+        HIPCHK(launch_trsm(prec, Np, k0, W, f.A, lda, LTj, f.inv, f.flags, s));
+        const int W1 = (int)std::min<int64_t>(NB_OUT, Np - kend);
+        HIPCHK(launch_gemm_sub(prec, Np - kend, W1, W, Lbelow, NB_OUT, at(k0, kend), lda,
+                               at(kend, kend), lda, f.flags, true, s));
+        tag0 += NB_OUT / NB_LEAF;
+        const int64_t rest = Np - kend - W1;
+        if (rest > 0) {
+            HIPCHK(launch_top_gemm(prec, kend, W1, f.A, lda, LTb[(j + 1) & 1], f.pub, f.inv, f.flags,
+                                   tag0, Np - kend, rest, W, Lbelow, NB_OUT, at(k0, kend + W1),
+                                   lda, at(kend, kend + W1), lda, s));
+        } else {
+            HIPCHK(launch_top(prec, kend, W1, f.A, lda, LTb[(j + 1) & 1], f.pub, f.inv, f.flags,
+                              tag0, s));
+        }
+    }
+    return 0;
+}
+
 // Explicit partial pivoting, blocked like getrf_spec, except that rows to
 // the right of an outer block are touched only once the whole block is
 // pivoted (a later leaf may interchange a row of the block with one below it).
@@ -235,7 +289,8 @@ int getrf_run(const FactorWs &f, hipStream_t s, Refill refill, FactorResult *res
 {
     int h[NFLAGS];
     HIPCHK(launch_fill_i32(f.flags, 0, NFLAGS, s));
-    CHK(getrf_spec(f, s));
+    if (top_path(f.prec)) CHK(getrf_spec_top(f, s));
+    else CHK(getrf_spec(f, s));
     // identity interchanges, queued before the wait (the pivoting path
     // overwrites every entry if it runs)
     HIPCHK(launch_iota_i32(f.ipiv, f.Np, s));

@@ -185,6 +185,22 @@ hipError_t launch_gemm_pair(int prec, int64_t M1, int64_t N1, const void *At1, i
 hipError_t launch_gemm_sub(int prec, int64_t M, int64_t N, int64_t K, const void *At,
                            int64_t ldat, const void *B, int64_t ldb, void *C, int64_t ldc,
                            int *flags, bool check_abort, hipStream_t s);
+// no-interchange factorisation of one outer block (FP16 / BF16): the
+// diagonal square (k_top) and the two triangular solves beside it (k_trsm);
+// top_pub_words / top_inv_floats size their publication area and the
+// inverses' side buffer
+size_t top_pub_words();
+size_t top_inv_floats();
+hipError_t launch_top(int prec, int64_t k0, int W, void *A, int64_t lda, void *LT, uint64_t *pub,
+                      float *inv, int *flags, uint32_t tag0, hipStream_t s);
+// the next block's square (k_top) fused with the rest of this block's
+// trailing update C[M x N] -= At^T B (256x256 tiles; M, N multiples of 256)
+hipError_t launch_top_gemm(int prec, int64_t k0, int W, void *A, int64_t lda, void *LT,
+                           uint64_t *pub, float *inv, int *flags, uint32_t tag0, int64_t M,
+                           int64_t N, int64_t K, const void *At, int64_t ldat, const void *B,
+                           int64_t ldb, void *C, int64_t ldc, hipStream_t s);
+hipError_t launch_trsm(int prec, int64_t Np, int64_t k0, int W, void *A, int64_t lda, void *LT,
+                       const float *inv, int *flags, hipStream_t s);
 // pivoting path: exchange area size (bytes), its reset, the cooperative leaf
 // panel, the row moves of its interchanges, the LT rebuild of an outer block
 size_t pivot_xch_bytes(int prec, int64_t Np);
