@@ -9,7 +9,12 @@ Jacobian stored in FP32 and an FP16 LU reused by iterative refinement
 Printed (one JSON line): time per solve, the same solve with an FP64 LU
 (Newton with a double-precision factorisation) on the same GPU, the
 factorisation's fraction of the FP16 matrix-core peak, and the CPU oracle
-timed on a bounded sample on this host's cores.
+timed on two bounded samples on this host's cores.
+
+Other modes: --serve (the batched engine on a seeded request stream) and
+--precision (the LU precisions compared on the paper's workloads against
+the stored oracle results; one JSON line per run, optionally a markdown
+table).
 """
 import argparse
 import json
@@ -36,7 +41,9 @@ def parse():
     ap.add_argument("--solver", default="IR", choices=["IR", "GMRES_IR", "DIRECT"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-LU Newton comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-n", type=int, default=6144, help="oracle sample size (about 10-20 s of host work)")
+    ap.add_argument("--cpu-n", type=int, default=6144,
+                    help="larger oracle sample size (about 10-20 s of host work); the smaller "
+                         "sample is 2/3 of it")
     ap.add_argument("--no-mf", action="store_true",
                     help="skip the FFT / matrix-free comparison solve")
     ap.add_argument("--copy-calib", action="store_true",
@@ -47,6 +54,13 @@ def parse():
     ap.add_argument("--rate", type=float, default=1000.0, help="arrivals per second")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--pool-gib", type=float, default=8.0, help="HBM budget for admitted requests")
+    ap.add_argument("--precision", action="store_true",
+                    help="LU precision comparison on the H-equation and dense tanh workloads")
+    ap.add_argument("--precision-only", choices=["all", "heq", "dense"], default="all")
+    ap.add_argument("--precision-quick", action="store_true",
+                    help="N=4096 H-equation and N=1024 dense only")
+    ap.add_argument("--precision-md", default=None, help="also write the table as markdown here")
+    ap.add_argument("--reps", type=int, default=3, help="timed solves per precision run")
     return ap.parse_args()
 
 
@@ -107,32 +121,197 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def precision_bench(args):
+    """The LU precisions compared on the paper's workloads (one JSON line per
+    run, and optionally a markdown table).
+
+    * H-equation (eq. (3.2)), x0 = ones: FP16 / BF16 / FP32 LU with IR and
+      the FP64-LU Newton at N = 4096 and 16384, c in {0.5, 0.9, 0.99}; the
+      ill-conditioned N = 8192, c in {0.9999, 0.99999} with GMRES-IR and IR.
+      References are the stored oracle results (tests/golden/oracle_heq_*):
+      its FP64 Newton count, and its iterate sampled at 257 points (error =
+      max over the samples of |x - x_ref| / max|x_ref|).
+    * Dense tanh system F(x) = A x + 0.1 tanh(x) - b with cond(A) in
+      {1e2, 1e4, 1e6}: x* = 1 exactly (error = max |x - 1|); the count is
+      set against the FP64-LU Newton on the same matrix.
+    """
+    import numpy as np
+    import torch
+    import paper_2307_16051_amd as n3p
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import golden_heq as G
+    from workloads import dense_tanh_system, dense_tanh_system_torch
+
+    rows = []
+
+    def emit(row):
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+
+    def timed(fn):
+        """Median time of args.reps solves after an untimed first one; a first
+        solve over 2 s (non-converging runs) is reported as it is."""
+        def once():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            return r, (time.perf_counter() - t0) * 1e3
+        rep, ms0 = once()
+        if ms0 > 2000.0:
+            return rep, ms0
+        ts = []
+        for _ in range(args.reps):
+            rep, ms = once()
+            ts.append(ms)
+        return rep, float(np.median(ts))
+
+    def heq(n, c, combos):
+        g = G.read(n, c)
+        idx = torch.from_numpy(g["idx"]).cuda()
+        alpha = 2.0 * (1.0 - np.sqrt(1.0 - c)) / c
+        for prec, solver in combos:
+            opts = n3p.Options.default()
+            ws = torch.empty(n3p.workspace_size(n, getattr(n3p, prec), getattr(n3p, solver), opts),
+                             dtype=torch.uint8, device="cuda")
+            x = torch.empty(n, dtype=torch.float64, device="cuda")
+
+            def go():
+                x.fill_(1.0)
+                return n3p.solve_heq(n, c, x=x, prec=getattr(n3p, prec),
+                                     solver=getattr(n3p, solver), opts=opts, ws=ws)[1]
+            rep, ms = timed(go)
+            xs = x[idx].cpu().numpy()
+            emit(dict(problem="heq", n=n, c=c, prec=prec, solver=solver, status=rep.status,
+                      its=rep.its, its_ref=g["its"], its_ref_src="oracle FP64 Newton (stored)",
+                      err=float(np.abs(xs - g["x"]).max() / np.abs(g["x"]).max()),
+                      moment_err=abs(float(x.mean().item()) - alpha), ms=ms,
+                      lin_its=rep.lin_its, final_rel_resid=rep.resid_rel[-1]))
+            del ws, x
+
+    def dense(n, cond, combos):
+        if n <= 2048:
+            A_np, b_np, _ = dense_tanh_system(n, cond)
+            A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
+            b = torch.from_numpy(b_np).cuda()
+        else:
+            A, b, _ = dense_tanh_system_torch(n, cond, "cuda")
+        its64 = None
+        for prec, solver in [("FP64", "DIRECT")] + [cs for cs in combos if cs[0] != "FP64"]:
+            opts = n3p.Options.default()
+            ws = torch.empty(n3p.workspace_size(n, getattr(n3p, prec), getattr(n3p, solver), opts),
+                             dtype=torch.uint8, device="cuda")
+            x = torch.empty(n, dtype=torch.float64, device="cuda")
+
+            def go():
+                x.zero_()
+                return n3p.solve_dense_tanh(A, b, x, prec=getattr(n3p, prec),
+                                            solver=getattr(n3p, solver), opts=opts, ws=ws)[1]
+            rep, ms = timed(go)
+            if prec == "FP64":
+                its64 = rep.its
+            emit(dict(problem="dense_tanh", n=n, cond=cond, prec=prec, solver=solver,
+                      status=rep.status, its=rep.its, its_ref=its64,
+                      its_ref_src="FP64-LU Newton on the GPU (context)",
+                      err=float((x - 1.0).abs().max().item()), ms=ms, lin_its=rep.lin_its,
+                      pivoted=any(rep.pivoted), final_rel_resid=rep.resid_rel[-1]))
+            del ws, x
+        del A, b
+
+    if args.precision_only in ("all", "heq"):
+        ir_combos = [("FP16", "IR"), ("BF16", "IR"), ("FP32", "IR"), ("FP64", "DIRECT")]
+        for n in ([4096] if args.precision_quick else [4096, 16384]):
+            for c in (0.5, 0.9, 0.99):
+                heq(n, c, ir_combos)
+        if not args.precision_quick:
+            for c in (0.9999, 0.99999):
+                heq(8192, c, [("FP16", "GMRES_IR"), ("FP16", "IR"), ("BF16", "GMRES_IR"),
+                              ("FP64", "DIRECT")])
+    if args.precision_only in ("all", "dense"):
+        dn = 1024 if args.precision_quick else 16384
+        for cond in (1e2, 1e4, 1e6):
+            dense(dn, cond, [("FP16", "IR"), ("FP16", "GMRES_IR"), ("BF16", "IR"),
+                             ("BF16", "GMRES_IR")])
+    if args.precision_md:
+        write_precision_md(rows, args.precision_md, " ".join(["python bench.py"] + sys.argv[1:]))
+
+
+def write_precision_md(rows, path, cmd):
+    lines = ["# LU precision comparison (measured on one MI355X)", "",
+             "Command:", "", "```", cmd, "```", "",
+             "H-equation error: max over the 257 stored samples of |x - x_ref| / max |x_ref|, "
+             "x_ref the oracle's FP64 Newton iterate (tests/golden/oracle_heq_*.txt; at "
+             "N = 16384 the iterate that meets the stopping rule, elsewhere the one driven to "
+             "the rounding floor); reference count: that oracle run.  Dense tanh: x* = 1, "
+             "error max |x - 1|; reference count: FP64-LU Newton on the GPU, for context.  "
+             "Status 1 = not converged in 20 Newton steps.", "",
+             "| problem | N | c / cond | LU | solver | status | its (ref) | error | "
+             "ms / solve | linear its |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        par = r.get("c", r.get("cond"))
+        ref = "-" if r["its_ref"] is None else str(r["its_ref"])
+        lines.append("| %s | %d | %g | %s | %s | %d | %d (%s) | %.2e | %.1f | %s |" % (
+            r["problem"], r["n"], par, r["prec"], r["solver"], r["status"], r["its"], ref,
+            r["err"], r["ms"], ",".join(str(v) for v in r["lin_its"])))
+    lines += ["", "Raw rows (JSON):", "", "```"] + [json.dumps(r) for r in rows] + ["```", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def cpu_baseline(n_sample: int, n_target: int, c: float):
-    """Oracle FP64 Newton on a bounded sample, scaled to the target size by N^3."""
+    """Oracle FP64 Newton on two bounded samples (2/3 n_sample and n_sample),
+    extrapolated to the target size with the exponent fitted to the two
+    measured times (the O(N^3) LU dominates, but cache and threading effects
+    make the small-size exponent differ from 3)."""
+    import math
     from oracle import oracle as O
-    t0 = time.perf_counter()
-    r = O.newton_heq(n_sample, c, floor=False)
-    dt = time.perf_counter() - t0
-    scale = (n_target / n_sample) ** 3
-    return {"value": dt * 1e3 * scale, "unit": "ms", "cores": O.num_threads(), "kind": "oracle",
-            "sample": "oracle FP64 Newton (own LU), H-equation N=%d c=%g, %d iterations, %.2f s "
-                      "measured, scaled by (%d/%d)^3 to N=%d" % (
-                          n_sample, c, r.its, dt, n_target, n_sample, n_target)}
+    sizes = [int(round(n_sample * 2 / 3 / 64)) * 64, n_sample]
+    samples = []
+    for ns in sizes:
+        t0 = time.perf_counter()
+        r = O.newton_heq(ns, c, floor=False)
+        samples.append({"n": ns, "s": time.perf_counter() - t0, "its": r.its})
+    (a, b) = samples
+    p = math.log(b["s"] / a["s"]) / math.log(b["n"] / a["n"])
+    value = b["s"] * 1e3 * (n_target / b["n"]) ** p
+    return {"value": value, "unit": "ms", "cores": O.num_threads(), "kind": "oracle",
+            "samples": samples, "fitted_exponent": p,
+            "value_cubic_scaling": b["s"] * 1e3 * (n_target / b["n"]) ** 3,
+            "sample": "oracle FP64 Newton (own LU), H-equation c=%g: N=%d in %.2f s (%d its) and "
+                      "N=%d in %.2f s (%d its); time ~ N^%.2f fitted to the two, extrapolated "
+                      "to N=%d" % (c, a["n"], a["s"], a["its"], b["n"], b["s"], b["its"], p,
+                                   n_target)}
 
 
-def measured_mfma_peak(n3p, torch, prec, blocks=2048, iters=256):
+def measured_mfma_peak(n3p, torch, prec, blocks=2048, min_ms=10.0):
     """The matrix-core rate on this device (TFLOP/s): back-to-back 32x32x16
-    MFMA chains on register operands, timed with events on the current stream."""
-    n3p.mfma_rate_probe(prec, blocks, 8)  # warm-up (code load)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    out, flops = n3p.mfma_rate_probe(prec, blocks, iters)
-    e1.record()
-    torch.cuda.synchronize()
-    if not bool((out == 2.0 * iters).all()):
-        raise RuntimeError("matrix-core rate probe returned wrong sums")
-    return flops / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    MFMA chains on register operands, timed with events on the current
+    stream.  The chain length is raised until one run takes at least min_ms;
+    the rate is the median of three such runs."""
+    import numpy as np
+
+    def run(iters):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out, flops = n3p.mfma_rate_probe(prec, blocks, iters)
+        e1.record()
+        torch.cuda.synchronize()
+        if not bool((out == 2.0 * iters).all()):
+            raise RuntimeError("matrix-core rate probe returned wrong sums")
+        return e0.elapsed_time(e1), flops
+
+    run(8)  # warm-up (code load)
+    iters = 256
+    ms, _ = run(iters)
+    while ms < min_ms and iters < (1 << 20):
+        iters = min(1 << 20, int(iters * max(2.0, 1.2 * min_ms / max(ms, 1e-3))))
+        ms, _ = run(iters)
+    rates, times = [], []
+    for _ in range(3):
+        ms, flops = run(iters)
+        rates.append(flops / (ms * 1e-3) / 1e12)
+        times.append(ms)
+    return float(np.median(rates)), {"iters": iters, "ms": times, "tflops": rates}
 
 
 def main():
@@ -144,6 +323,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_bench(args)
+        return
+    if args.precision:
+        precision_bench(args)
         return
     import numpy as np
     import torch
@@ -213,8 +395,9 @@ def main():
                      "kernel": "getrf (whole factorisation, (2/3)N^3 flop)", "padded_n": Np},
     }
     if args.prec in ("FP16", "BF16"):
-        pk = measured_mfma_peak(n3p, torch, prec)
+        pk, runs = measured_mfma_peak(n3p, torch, prec)
         out["roofline"]["peak_measured"] = pk
+        out["roofline"]["peak_measured_runs"] = runs
         out["roofline"]["frac_of_measured"] = achieved / pk if pk else None
     # the same solve with the O(N log N) residual and operator-based J v
     # (no stored FP32 Jacobian), for comparison

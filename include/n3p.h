@@ -117,6 +117,13 @@ typedef struct n3p_options {
                                 (J v = v - diag(1/D^2) K v by FFT in FP64, rounded to
                                 FP32) instead of the stored FP32 J, which is then not
                                 formed (4 N^2 fewer bytes); N <= 32768; default 0 */
+    int ir_scaled_half;      /* IR only (N3P_E_INVALID with another solver): 1 = each
+                                correction by eq. (2.19) (Section 2.3),
+                                d = ||r|| I_h^s(U^{-1} L^{-1} I_s^h(r/||r||)): the unit-
+                                scaled residual and every entry of the triangular
+                                solves' results rounded to the factor precision
+                                (sums in FP32); 0 (default) = the factors promoted to
+                                FP32 on the fly, eq. (2.16) */
 } n3p_options;
 
 /* Fill *opt with the defaults listed above. */
@@ -302,6 +309,17 @@ N3P_API int n3p_ir(int prec, int64_t n, const float *A, int64_t lda, const void 
                    float *u, double tol, int max_sweeps, int *sweeps, int *failed,
                    double *rel_res, void *ws, size_t ws_bytes, void *stream);
 
+/* n3p_ir with each correction formed by eq. (2.19) (Section 2.3): r scaled to
+ * unit 2-norm and rounded to the factor precision, both triangular solves
+ * with every solution entry rounded to that precision as it is formed (sums
+ * in FP32), the result promoted and multiplied by ||r||.  Same arguments,
+ * workspace, stopping rule and errors as n3p_ir.  Synchronises the stream. */
+N3P_API int n3p_ir_scaled_half(int prec, int64_t n, const float *A, int64_t lda, const void *LU,
+                               int64_t ldlu, const int32_t *ipiv, const float *colscale,
+                               const float *b, float *u, double tol, int max_sweeps, int *sweeps,
+                               int *failed, double *rel_res, void *ws, size_t ws_bytes,
+                               void *stream);
+
 /* GMRES-IR: as n3p_ir, but each correction solves M^{-1} A d = M^{-1} r
  * (M = the low-precision LU) with restarted GMRES(m), modified Gram-Schmidt,
  * relative tolerance gmres_tol (end of Section 2.2).  *gmres_its (host)
@@ -369,7 +387,8 @@ N3P_API void n3p_engine_default_config(n3p_engine_config *cfg);
 N3P_API size_t n3p_engine_request_bytes(int64_t n, int lu_prec);
 /* Pool bytes the engine itself keeps for max_slots slots (the slot table). */
 N3P_API size_t n3p_engine_fixed_bytes(int max_slots);
-/* pool: caller-owned device memory, kept until destroy; opt may be NULL. */
+/* pool: caller-owned device memory, kept until destroy; opt may be NULL
+ * (opt->ir_scaled_half must be 0: the engine's IR promotes on the fly). */
 N3P_API int n3p_engine_create(n3p_engine **e, const n3p_engine_config *cfg,
                               const n3p_options *opt, void *pool, size_t pool_bytes,
                               void *stream);

@@ -12,13 +12,20 @@ SRC = os.path.join(HERE, "n3p_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
-           "-o", LIB, SRC, "-lm"]
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose: bool = False, out: str = LIB, sanitize: bool = False) -> str:
+    """sanitize: an AddressSanitizer + UndefinedBehaviorSanitizer build (load
+    it with gcc's libasan preloaded and N3P_ORACLE_LIB=<out>)."""
+    opt = SANITIZE if sanitize else ["-O2"]
+    cmd = ["gcc"] + opt + ["-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+                           "-o", out, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

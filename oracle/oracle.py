@@ -31,7 +31,9 @@ from typing import Callable, List, Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# N3P_ORACLE_LIB: another build of n3p_oracle.c (the sanitizer test loads an
+# AddressSanitizer / UndefinedBehaviorSanitizer build this way)
+_LIB_PATH = os.environ.get("N3P_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -316,6 +318,27 @@ class HalfLU:
                                  unit_diagonal=True, check_finite=False)
         return sla.solve_triangular(U, y, lower=False, check_finite=False).astype(work)
 
+    def solve_half(self, r: np.ndarray) -> np.ndarray:
+        """U^{-1} L^{-1} P I_s^h(r) held in the factor precision (Section 2.3).
+
+        The correction of eq. (2.19) solves "entirely in the lower precision":
+        the right-hand side is rounded to the factor precision, and forward
+        then back substitution form each solution entry from the entries
+        before it with the sum taken in FP64 and rounded once to the factor
+        precision (the same single rounding per stored value as the
+        factorisation), before later entries use it.  Returns FP32.
+        """
+        h = _HALF[self.prec]
+        n = len(r)
+        z = np.asarray(r, dtype=np.float32).astype(h).astype(np.float64)[self.perm]
+        y = np.zeros(n)
+        for i in range(n):
+            y[i] = h(z[i] - self.L[i, :i] @ y[:i])
+        x = np.zeros(n)
+        for i in range(n - 1, -1, -1):
+            x[i] = h((y[i] - self.U[i, i + 1:] @ x[i + 1:]) / self.U[i, i])
+        return x.astype(np.float32)
+
 
 @dataclasses.dataclass
 class IRResult:
@@ -326,13 +349,15 @@ class IRResult:
 
 
 def ir(A32: np.ndarray, b: np.ndarray, lu: HalfLU, max_sweeps: int = 10, tol: float = 1e-6,
-       u0: Optional[np.ndarray] = None) -> IRResult:
+       u0: Optional[np.ndarray] = None, scaled_half: bool = False) -> IRResult:
     """Iterative refinement (Section 2.2), with the stopping policy of Section 3.1.
 
     r = b - A u;  while ||r|| too large: d = U^{-1} L^{-1} r;  u += d;  r = b - A u.
     Success when ||r|| < tol ||b||; failure when ||r|| increases, in which case
     the iterate with the best residual is returned.  A, b, u, r, d are single
-    precision; the factors are half precision promoted on the fly.
+    precision; the factors are half precision promoted on the fly, or, with
+    ``scaled_half``, each correction is eq. (2.19) (Section 2.3):
+    d = ||r|| I_h^s(U^{-1} L^{-1} I_s^h(r / ||r||)), ||.|| the 2-norm.
     """
     A32 = np.asarray(A32, dtype=np.float32)
     b = np.asarray(b, dtype=np.float32)
@@ -344,7 +369,11 @@ def ir(A32: np.ndarray, b: np.ndarray, lu: HalfLU, max_sweeps: int = 10, tol: fl
     sweeps = 0
     failed = False
     while rn >= tol * nb and sweeps < max_sweeps:
-        d = lu.solve(r, np.float32)
+        if scaled_half and rn > 0:
+            d = (rn * lu.solve_half((r.astype(np.float64) / rn).astype(np.float32))
+                 .astype(np.float64)).astype(np.float32)
+        else:
+            d = lu.solve(r, np.float32)
         u = (u + d).astype(np.float32)
         r = (b - A32 @ u).astype(np.float32)
         sweeps += 1

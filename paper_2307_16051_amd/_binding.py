@@ -20,11 +20,13 @@ SCALE_AUTO, SCALE_NONE = 0, 1
 MAX_HIST = 64
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-lib_path = os.path.join(_HERE, "libn3p.so")
+# N3P_LIB: another build of the same sources (the sanitizer test loads a
+# host-side AddressSanitizer build this way); there is no fallback
+lib_path = os.environ.get("N3P_LIB") or os.path.join(_HERE, "libn3p.so")
 
 if not os.path.exists(lib_path):
     raise ImportError(
-        "libn3p.so is not built (%s); run `python -c \"import __graft_entry__ as g; g.build()\"`"
+        "the n3p library is not built (%s); run `python -c \"import __graft_entry__ as g; g.build()\"`"
         % lib_path)
 
 lib = ctypes.CDLL(lib_path)
@@ -41,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("tau_r", _f64), ("tau_a", _f64), ("tau_abs_override", _f64), ("eta", _f64),
                 ("maxit", _int), ("max_ir_sweeps", _int), ("gmres_restart", _int),
                 ("gmres_tol", _f64), ("gmres_max_restarts", _int), ("scale_mode", _int),
-                ("timing", _int), ("fft_residual", _int), ("matrix_free", _int)]
+                ("timing", _int), ("fft_residual", _int), ("matrix_free", _int),
+                ("ir_scaled_half", _int)]
 
     @classmethod
     def default(cls, **kw) -> "Options":
@@ -133,6 +136,7 @@ def _setup():
     L.n3p_linsolve_workspace_size.restype = ctypes.c_size_t
     L.n3p_ir.argtypes = [_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _f64, _int, _ip, _ip,
                          _dp, _vp, ctypes.c_size_t, _vp]
+    L.n3p_ir_scaled_half.argtypes = L.n3p_ir.argtypes
     L.n3p_gmres_ir.argtypes = [_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _f64, _int,
                                _int, _f64, _ip, _ip, _ip, _dp, _vp, ctypes.c_size_t, _vp]
     L.n3p_mfma_rate_probe.argtypes = [_int, _int, _int, _vp, _dp, _vp]
@@ -140,7 +144,8 @@ def _setup():
     for name in ("n3p_problem_heq", "n3p_problem_dense_tanh", "n3p_problem_callbacks",
                  "n3p_solve", "n3p_getrf", "n3p_getrs", "n3p_gemv_resid_f32",
                  "n3p_gemv_resid_f32_noalloc", "n3p_heq_residual",
-                 "n3p_heq_jacobian", "n3p_ir", "n3p_gmres_ir", "n3p_mfma_rate_probe"):
+                 "n3p_heq_jacobian", "n3p_ir", "n3p_ir_scaled_half", "n3p_gmres_ir",
+                 "n3p_mfma_rate_probe"):
         getattr(L, name).restype = _int
 
 
@@ -319,14 +324,17 @@ def _lin_args(A, LU, ipiv, colscale, prec):
 
 
 def ir(A: torch.Tensor, LU: torch.Tensor, ipiv, b: torch.Tensor, u: torch.Tensor,
-       tol: float = 1e-6, max_sweeps: int = 10, colscale=None, prec: Optional[int] = None):
-    """n3p_ir; returns (sweeps, failed, rel_res); u is updated in place."""
+       tol: float = 1e-6, max_sweeps: int = 10, colscale=None, prec: Optional[int] = None,
+       scaled_half: bool = False):
+    """n3p_ir (scaled_half: n3p_ir_scaled_half, the corrections of eq. (2.19));
+    returns (sweeps, failed, rel_res); u is updated in place."""
     n, prec, pp, cp = _lin_args(A, LU, ipiv, colscale, prec)
     ws = _ws(lib.n3p_linsolve_workspace_size(n, 1), A.device)
     sw, fl, rr = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-    _check(lib.n3p_ir(prec, n, _ptr(A), n, _ptr(LU), n, pp, cp, _ptr(b), _ptr(u), tol, max_sweeps,
-                      ctypes.byref(sw), ctypes.byref(fl), ctypes.byref(rr), _ptr(ws), ws.numel(),
-                      _stream()), "n3p_ir")
+    fn, name = (lib.n3p_ir_scaled_half, "n3p_ir_scaled_half") if scaled_half else (lib.n3p_ir, "n3p_ir")
+    _check(fn(prec, n, _ptr(A), n, _ptr(LU), n, pp, cp, _ptr(b), _ptr(u), tol, max_sweeps,
+              ctypes.byref(sw), ctypes.byref(fl), ctypes.byref(rr), _ptr(ws), ws.numel(),
+              _stream()), name)
     return sw.value, bool(fl.value), rr.value
 
 

@@ -32,9 +32,17 @@ def common_flags():
             "-Wno-unused-result", "-Wno-unused-command-line-argument"]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + common_flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+# Host-side AddressSanitizer / UndefinedBehaviorSanitizer flags (CPU code
+# only: each applies to the host compilation, never to gfx950 code)
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+HOST_SOURCES = ["n3p_api.cpp", "n3p_batch.cpp"]
+
+
+def _compile(src: str, verbose: bool, out_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [hipcc()] + common_flags() + list(extra) + ["-x", "hip", "-c", os.path.join(CSRC, src),
+                                                      "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,6 +66,29 @@ def build(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """A copy of the library whose host driver code (HOST_SOURCES) is built
+    with HOST_SANITIZE, linked with the kernel objects of the last build().
+    Load it with the compiler's ASan runtime preloaded (N3P_LIB=<path>)."""
+    objs = []
+    for src in SOURCES:
+        if src in HOST_SOURCES:
+            objs.append(_compile(src, verbose, out_dir, HOST_SANITIZE))
+        else:
+            obj = os.path.join(BUILD, src + ".o")
+            if not os.path.exists(obj):
+                raise RuntimeError("build() first: %s is missing" % obj)
+            objs.append(obj)
+    lib = os.path.join(out_dir, "libn3p_host_asan.so")
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-shared-libsan",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-o", lib] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return lib
 
 
 if __name__ == "__main__":

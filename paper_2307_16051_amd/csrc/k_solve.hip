@@ -233,6 +233,10 @@ __device__ __forceinline__ void load_row(V (&r)[BS], const V *__restrict__ R, in
 }
 
 // ---------------------------------------------------------------- lower
+// round_out (both solves): every solution entry is rounded to the factor
+// type T as it is formed, before later blocks use it -- the solve held in
+// the low precision for the scaled correction of eq. (2.19) (Section 2.3).
+//
 // y = L^{-1} (P b): L unit lower (below the diagonal of LU), perm[i] = the
 // original row placed at position i (null = identity).  Block `blk` owns rows
 // [blk*BS, blk*BS + BS) (lane = row); wavefront w consumes tiles w, w+4, ...
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
                                                     const int32_t *__restrict__ perm,
                                                     const V *__restrict__ b, V *__restrict__ y,
                                                     int *__restrict__ sync, uint32_t epoch,
-                                                    int *__restrict__ flags)
+                                                    int *__restrict__ flags, int round_out)
 {
     static_assert(BS == 64, "a wavefront spans one tile");
     __shared__ int s_blk;
@@ -312,6 +316,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
             xp.settle(tags, (int64_t)last * BS + lane, true, epoch, &spins, flags);
             w -= row_times_lanes<V, BS>(rr, xp.value());
         }
+        if (round_out) w = (V)to_f32((T)w);  // solution held in the factor precision
         if (rv) {
             y[row] = w;
             tagged<V>::put(tags, row, w, epoch);
@@ -328,7 +333,8 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
                                                     const V *__restrict__ yin,
                                                     const float *__restrict__ colscale,
                                                     V *__restrict__ x, int *__restrict__ sync,
-                                                    uint32_t epoch, int *__restrict__ flags)
+                                                    uint32_t epoch, int *__restrict__ flags,
+                                                    int round_out)
 {
     static_assert(BS == 64, "a wavefront spans one tile");
     __shared__ int s_blk;
@@ -401,6 +407,7 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
             xn.settle(tags, (int64_t)next * BS + lane, valid, epoch, &spins, flags);
             w -= row_times_lanes<V, BS>(rr, valid ? xn.value() : (V)0);
         }
+        if (round_out) w = (V)to_f32((T)w);
         if (rv) {
             tagged<V>::put(tags, row, w, epoch);
             x[row] = colscale ? w * (V)colscale[row] : w;
@@ -416,51 +423,74 @@ size_t trsv_sync_ints(int64_t n) { return (size_t)(4 + 4 * n); }
 template <typename T, typename V>
 static hipError_t trsv_lower_t(int64_t n, const void *LU, int64_t lda, const int32_t *perm,
                                const V *b, V *y, int *sync, uint32_t epoch, int *flags,
-                               hipStream_t s)
+                               hipStream_t s, int round_out = 0)
 {
     const unsigned nb = (unsigned)((n + TRSV_BS - 1) / TRSV_BS);
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(1), 0, s, sync);
     hipLaunchKernelGGL((k_trsv_lower<T, V, TRSV_BS>), dim3(nb), dim3(256), 0, s, n, (const T *)LU,
-                       lda, perm, b, y, sync, epoch, flags);
+                       lda, perm, b, y, sync, epoch, flags, round_out);
     return hipGetLastError();
 }
 
 template <typename T, typename V>
 static hipError_t trsv_upper_t(int64_t n, const void *LU, int64_t lda, const V *y,
                                const float *colscale, V *x, int *sync, uint32_t epoch, int *flags,
-                               hipStream_t s)
+                               hipStream_t s, int round_out = 0)
 {
     const unsigned nb = (unsigned)((n + TRSV_BS - 1) / TRSV_BS);
     hipLaunchKernelGGL(k_zero_ticket, dim3(1), dim3(1), 0, s, sync);
     hipLaunchKernelGGL((k_trsv_upper<T, V, TRSV_BS>), dim3(nb), dim3(256), 0, s, n, (const T *)LU,
-                       lda, y, colscale, x, sync, epoch, flags);
+                       lda, y, colscale, x, sync, epoch, flags, round_out);
     return hipGetLastError();
 }
 
 hipError_t launch_trsv_lower(int prec, int64_t n, const void *LU, int64_t lda, const int32_t *perm,
                              const float *b, float *y, int *sync, uint32_t epoch, int *flags,
-                             hipStream_t s)
+                             hipStream_t s, int round_out)
 {
     switch (prec) {
-    case N3P_FP16: return trsv_lower_t<f16, float>(n, LU, lda, perm, b, y, sync, epoch, flags, s);
-    case N3P_BF16: return trsv_lower_t<bf16, float>(n, LU, lda, perm, b, y, sync, epoch, flags, s);
-    case N3P_FP32: return trsv_lower_t<float, float>(n, LU, lda, perm, b, y, sync, epoch, flags, s);
-    case N3P_FP64: return trsv_lower_t<double, float>(n, LU, lda, perm, b, y, sync, epoch, flags, s);
+    case N3P_FP16: return trsv_lower_t<f16, float>(n, LU, lda, perm, b, y, sync, epoch, flags, s, round_out);
+    case N3P_BF16: return trsv_lower_t<bf16, float>(n, LU, lda, perm, b, y, sync, epoch, flags, s, round_out);
+    case N3P_FP32: return trsv_lower_t<float, float>(n, LU, lda, perm, b, y, sync, epoch, flags, s, round_out);
+    case N3P_FP64: return trsv_lower_t<double, float>(n, LU, lda, perm, b, y, sync, epoch, flags, s, round_out);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_trsv_upper(int prec, int64_t n, const void *LU, int64_t lda, const float *y,
                              const float *colscale, float *x, int *sync, uint32_t epoch, int *flags,
-                             hipStream_t s)
+                             hipStream_t s, int round_out)
 {
     switch (prec) {
-    case N3P_FP16: return trsv_upper_t<f16, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s);
-    case N3P_BF16: return trsv_upper_t<bf16, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s);
-    case N3P_FP32: return trsv_upper_t<float, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s);
-    case N3P_FP64: return trsv_upper_t<double, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s);
+    case N3P_FP16: return trsv_upper_t<f16, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s, round_out);
+    case N3P_BF16: return trsv_upper_t<bf16, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s, round_out);
+    case N3P_FP32: return trsv_upper_t<float, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s, round_out);
+    case N3P_FP64: return trsv_upper_t<double, float>(n, LU, lda, y, colscale, x, sync, epoch, flags, s, round_out);
     }
     return hipErrorInvalidValue;
+}
+
+// out = I_s^h(a * in): the scaled vector rounded to the factor type (held as
+// FP32 values), the right-hand side of the low-precision solves of eq. (2.19)
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_round(int64_t n, const float *__restrict__ in, float a,
+                                                     float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = to_f32((T)(in[i] * a));
+}
+
+hipError_t launch_scale_round(int prec, int64_t n, const float *in, float a, float *out, hipStream_t s)
+{
+    const unsigned g = (unsigned)((n + 255) / 256);
+    switch (prec) {
+    case N3P_FP16: hipLaunchKernelGGL(k_scale_round<f16>, dim3(g), dim3(256), 0, s, n, in, a, out); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_scale_round<bf16>, dim3(g), dim3(256), 0, s, n, in, a, out); break;
+    case N3P_FP32:
+    case N3P_FP64: hipLaunchKernelGGL(k_scale_round<float>, dim3(g), dim3(256), 0, s, n, in, a, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_trsv_lower_f64(int64_t n, const double *LU, int64_t lda, const int32_t *perm,

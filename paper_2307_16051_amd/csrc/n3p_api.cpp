@@ -493,6 +493,9 @@ struct LinCtx {
     const double *D;
     double c;
     int L;
+    // IR corrections by eq. (2.19): the solves run in the factor precision
+    // on the residual scaled to unit norm (Section 2.3)
+    bool ir_half = false;
 };
 
 // r = b - A u  (A stored FP32, or the H-equation operator when matrix-free)
@@ -522,6 +525,19 @@ int apply_prec(LinCtx &c, const float *in, float *out)
                              c.flags, c.s));
     HIPCHK(launch_trsv_upper(c.prec, c.n, c.LU, c.ldlu, c.y, c.colscale, out, c.sync,
                              c.epoch->next(), c.flags, c.s));
+    return 0;
+}
+
+// out = rn * I_h^s(U^{-1} L^{-1} I_s^h(in / rn)) (eq. (2.19)): the scaled
+// right-hand side and every solution entry rounded to the factor type
+int apply_prec_half(LinCtx &c, const float *in, double rn, float *out)
+{
+    HIPCHK(launch_scale_round(c.prec, c.n, in, (float)(1.0 / rn), c.z, c.s));
+    HIPCHK(launch_trsv_lower(c.prec, c.n, c.LU, c.ldlu, c.perm, c.z, c.y, c.sync, c.epoch->next(),
+                             c.flags, c.s, 1));
+    HIPCHK(launch_trsv_upper(c.prec, c.n, c.LU, c.ldlu, c.y, c.colscale, out, c.sync,
+                             c.epoch->next(), c.flags, c.s, 1));
+    HIPCHK(launch_scal_copy_f32(c.n, out, out, rn, c.s));
     return 0;
 }
 
@@ -634,7 +650,8 @@ int refine(LinCtx &c, const float *b, float *u, double tol, int max_sweeps, bool
             CHK(gmres_lp(c, c.r, c.d, m, gtol, max_restarts, &its));
             o->inner += its;
         } else {
-            CHK(apply_prec(c, c.r, c.d));
+            if (c.ir_half && rn > 0.0) CHK(apply_prec_half(c, c.r, rn, c.d));
+            else CHK(apply_prec(c, c.r, c.d));
             o->inner += 1;
         }
         HIPCHK(launch_vcopy_f32(c.n, c.uprev, u, c.s));
@@ -695,6 +712,7 @@ N3P_API void n3p_default_options(n3p_options *o)
     o->timing = 1;
     o->fft_residual = 0;
     o->matrix_free = 0;
+    o->ir_scaled_half = 0;
 }
 
 N3P_API int n3p_problem_heq(n3p_problem *p, int64_t n, double c)
@@ -807,7 +825,8 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
     else n3p_default_options(&opt);
     if (rep) std::memset(rep, 0, sizeof(*rep));
     if (!p || !x || !ws || !valid_prec(lu_prec) || ls < N3P_IR || ls > N3P_DIRECT || p->n < 1 ||
-        opt.maxit < 0 || opt.maxit >= N3P_MAX_HIST || opt.max_ir_sweeps < 1)
+        opt.maxit < 0 || opt.maxit >= N3P_MAX_HIST || opt.max_ir_sweeps < 1 ||
+        (opt.ir_scaled_half != 0 && (opt.ir_scaled_half != 1 || ls != N3P_IR)))
         return N3P_E_INVALID;
     const int m = opt_m(&opt);
     const int fm = fft_mode(&opt);
@@ -886,6 +905,7 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
     lc.y = w.y;
     lc.xs = w.xs;
     lc.z = w.z;
+    lc.ir_half = opt.ir_scaled_half == 1;
     lc.av = w.av;
     lc.w = w.w;
     lc.V = w.V;
@@ -1287,6 +1307,30 @@ N3P_API int n3p_ir(int prec, int64_t n, const float *A, int64_t lda, const void 
     LinCtx c{};
     Epoch ep;
     CHK(lin_common(prec, n, A, lda, LU, ldlu, ipiv, colscale, 1, ws, ws_bytes, s, &c, &ep));
+    LinOut o;
+    CHK(refine(c, b, u, tol, max_sweeps, false, false, 1, 0.0, 1, &o));
+    int h[NFLAGS];
+    HIPCHK(hipMemcpyAsync(h, c.flags, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h[FLAG_TIMEOUT]) return N3P_E_TIMEOUT;
+    if (sweeps) *sweeps = o.sweeps;
+    if (failed) *failed = o.failed ? 1 : 0;
+    if (rel_res) *rel_res = o.rel;
+    return N3P_OK;
+}
+
+N3P_API int n3p_ir_scaled_half(int prec, int64_t n, const float *A, int64_t lda, const void *LU,
+                               int64_t ldlu, const int32_t *ipiv, const float *colscale,
+                               const float *b, float *u, double tol, int max_sweeps, int *sweeps,
+                               int *failed, double *rel_res, void *ws, size_t ws_bytes,
+                               void *stream)
+{
+    if (!b || !u || max_sweeps < 1) return N3P_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    LinCtx c{};
+    Epoch ep;
+    CHK(lin_common(prec, n, A, lda, LU, ldlu, ipiv, colscale, 1, ws, ws_bytes, s, &c, &ep));
+    c.ir_half = true;
     LinOut o;
     CHK(refine(c, b, u, tol, max_sweeps, false, false, 1, 0.0, 1, &o));
     int h[NFLAGS];

@@ -386,7 +386,9 @@ N3P_API int n3p_engine_create(n3p_engine **out, const n3p_engine_config *cfg,
     n3p_options o;
     if (opt) o = *opt;
     else n3p_default_options(&o);
-    if (!valid_cfg(c) || !pool || o.maxit < 0 || o.max_ir_sweeps < 1) return N3P_E_INVALID;
+    // the engine's IR promotes the factors on the fly (no eq. (2.19) option)
+    if (!valid_cfg(c) || !pool || o.maxit < 0 || o.max_ir_sweeps < 1 || o.ir_scaled_half != 0)
+        return N3P_E_INVALID;
     char *base = (char *)(((uintptr_t)pool + BALIGN - 1) / BALIGN * BALIGN);
     const size_t lost = (size_t)(base - (char *)pool);
     const size_t fixed = fixed_bytes(c.max_slots);

@@ -223,12 +223,15 @@ hipError_t launch_mfma_rate(int prec, int blocks, int iters, float *out, double 
                             hipStream_t s);
 
 // triangular solves and matvec
+// round_out = 1: each solution entry rounded to the factor type as it is formed
 hipError_t launch_trsv_lower(int prec, int64_t n, const void *LU, int64_t lda, const int32_t *perm,
                              const float *b, float *y, int *sync, uint32_t epoch, int *flags,
-                             hipStream_t s);
+                             hipStream_t s, int round_out = 0);
 hipError_t launch_trsv_upper(int prec, int64_t n, const void *LU, int64_t lda, const float *y,
                              const float *colscale, float *x, int *sync, uint32_t epoch, int *flags,
-                             hipStream_t s);
+                             hipStream_t s, int round_out = 0);
+// out = in * a rounded to the factor type of prec (held as FP32)
+hipError_t launch_scale_round(int prec, int64_t n, const float *in, float a, float *out, hipStream_t s);
 hipError_t launch_trsv_lower_f64(int64_t n, const double *LU, int64_t lda, const int32_t *perm,
                                  const double *b, double *y, int *sync, uint32_t epoch,
                                  int *flags, hipStream_t s);

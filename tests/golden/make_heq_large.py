@@ -18,18 +18,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 from oracle import oracle as O  # noqa: E402
+from golden_heq import path_for, read, sample_index  # noqa: E402,F401
 
 CASES = [(4096, 0.5), (4096, 0.9), (4096, 0.99), (8192, 0.9999), (8192, 0.99999),
          (16384, 0.5), (16384, 0.9), (16384, 0.99)]
-NSAMPLE = 257
-
-
-def path_for(n, c):
-    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_heq_n%d_c%s.txt" % (n, repr(c)))
-
-
-def sample_index(n):
-    return np.unique(np.linspace(0, n - 1, NSAMPLE).round().astype(int))
 
 
 def write(n, c, floor=True):
@@ -55,29 +47,6 @@ def write(n, c, floor=True):
             f.write("x %d %r\n" % (i, float(xs[i])))
     print("wrote %s (%.0f s, its %d)" % (path_for(n, c), dt, r.its), flush=True)
 
-
-def read(n, c):
-    """Parsed golden file: dict(kind, its, rel_hist, mean, norm2, idx, x)."""
-    out = {"idx": [], "x": [], "kind": "floor"}
-    with open(path_for(n, c)) as f:
-        for line in f:
-            if line.startswith("#") or not line.strip():
-                continue
-            key, *vals = line.split()
-            if key == "kind":
-                out["kind"] = vals[0]
-            elif key == "its":
-                out["its"] = int(vals[0])
-            elif key == "rel_hist":
-                out["rel_hist"] = np.array([float(v) for v in vals])
-            elif key in ("mean", "norm2", "floor_mean", "floor_norm2"):
-                out[key.replace("floor_", "")] = float(vals[0])
-            elif key == "x":
-                out["idx"].append(int(vals[0]))
-                out["x"].append(float(vals[1]))
-    out["idx"] = np.array(out["idx"])
-    out["x"] = np.array(out["x"])
-    return out
 
 
 if __name__ == "__main__":

@@ -104,6 +104,28 @@ def test_mfma_rate_probe_rejects_bad_arguments(lib):
     assert lib.n3p_mfma_rate_probe(FP16, 1, 1, None, ctypes.byref(fl), None) == -1
 
 
+def test_scaled_half_option_is_ir_only():
+    """eq. (2.19) is an IR option (Section 2.3: it does not suffice for
+    GMRES-IR); other solvers, other values and the batched engine reject it
+    before any device work."""
+    import paper_2307_16051_amd as n3p
+    from paper_2307_16051_amd import _binding as B
+    p = B._Problem()
+    assert B.lib.n3p_problem_heq(ctypes.byref(p), 256, 0.9) == 0
+    x = (ctypes.c_double * 256)()
+    ws = (ctypes.c_char * 64)()
+    for solver, val in ((n3p.GMRES_IR, 1), (n3p.DIRECT, 1), (n3p.IR, 2), (n3p.IR, -1)):
+        o = n3p.Options.default(ir_scaled_half=val)
+        assert B.lib.n3p_solve(ctypes.byref(p), x, n3p.FP16, solver, ctypes.byref(o), ws,
+                               ctypes.sizeof(ws), None, None) == -1
+    cfg = n3p.EngineConfig()
+    B.lib.n3p_engine_default_config(ctypes.byref(cfg))
+    eng = ctypes.c_void_p()
+    o = n3p.Options.default(ir_scaled_half=1)
+    assert B.lib.n3p_engine_create(ctypes.byref(eng), ctypes.byref(cfg), ctypes.byref(o), ws,
+                                   ctypes.sizeof(ws), None) == -1
+
+
 def test_gemv_noalloc_rejects_bad_arguments(lib):
     """The allocation-free matvec validates sizes and pointers before it
     touches a device (no GPU here): n beyond the fixed scratch, n < 1, a

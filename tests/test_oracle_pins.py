@@ -294,3 +294,73 @@ def test_three_precision_gmres_ir_matches_f64_iterations_small():
         r64 = O.newton_heq(n, c)
         assert r3.its == r64.its
         assert np.linalg.norm(r3.x - r64.x_floor) / np.linalg.norm(r64.x_floor) < 1e-9
+
+
+# ------------------------------------------- the correction of eq. (2.19)
+
+def _factors(L, U, prec="fp16"):
+    lu = O.HalfLU.__new__(O.HalfLU)
+    lu.prec = prec
+    lu.L = np.asarray(L, dtype=np.float64)
+    lu.U = np.asarray(U, dtype=np.float64)
+    lu.perm = np.arange(lu.L.shape[0])
+    return lu
+
+
+def test_solve_half_hand_worked_2x2():
+    """Section 2.3: both solves held in FP16, by hand.  rhs (1, 1/3) rounds
+    to (1, 1365/4096); y1 = 1365/4096 - 1/2 = -683/4096 (exact in FP16);
+    x1 = y1 / 4 = -683/16384 (exact); x0 = (1 - x1) / 2 = 17067/32768, which
+    lies between the FP16 neighbours 1066/2048 and 1067/2048 and rounds up."""
+    lu = _factors([[1.0, 0.0], [0.5, 1.0]], [[2.0, 1.0], [0.0, 4.0]])
+    x = lu.solve_half(np.array([1.0, 1.0 / 3.0], dtype=np.float32))
+    assert x[0] == 1067.0 / 2048.0 and x[1] == -683.0 / 16384.0
+
+
+def test_solve_half_diagonal_closed_form():
+    """L = I, U = diag(d): each entry is round(round(r_i) / d_i)."""
+    rng = np.random.default_rng(7)
+    d = rng.uniform(0.5, 4.0, 64)
+    r = rng.standard_normal(64).astype(np.float32)
+    lu = _factors(np.eye(64), np.diag(d))
+    want = (r.astype(np.float16).astype(np.float64) / d).astype(np.float16).astype(np.float32)
+    assert np.array_equal(lu.solve_half(r), want)
+
+
+def test_solve_half_entries_in_fp16_and_close_to_exact_solve():
+    """Every entry is an FP16 number, and the result is the exact solve of
+    the rounded right-hand side up to a few FP16 roundings per entry (a
+    dropped term, a wrong index or a transposed factor fails by far more)."""
+    rng = np.random.default_rng(3)
+    n = 96
+    L = np.tril(rng.uniform(-0.5, 0.5, (n, n)) / n, -1) + np.eye(n)
+    U = np.triu(rng.uniform(-0.5, 0.5, (n, n)) / n, 1) + np.diag(rng.uniform(1.0, 2.0, n))
+    r = rng.standard_normal(n).astype(np.float32)
+    lu = _factors(L, U)
+    x = lu.solve_half(r)
+    assert np.array_equal(x.astype(np.float16).astype(np.float32), x)
+    exact = sla.solve_triangular(U, sla.solve_triangular(L, r.astype(np.float16).astype(np.float64),
+                                                         lower=True, unit_diagonal=True))
+    assert np.max(np.abs(x - exact)) <= 4 * 2.0 ** -11 * np.max(np.abs(exact))
+    # with FP32 storage the same routine is the FP32 rounding of the exact solve
+    x32 = _factors(L, U, "fp32").solve_half(r.astype(np.float16).astype(np.float32))
+    assert np.max(np.abs(x32 - exact)) <= 4 * 2.0 ** -24 * np.max(np.abs(exact))
+
+
+def test_scaled_half_ir_matches_on_the_fly_ir_when_well_conditioned():
+    """Section 2.3: the two ways of transferring precision give the same
+    results except for the most ill-conditioned problems -- same sweep
+    count and the same converged correction on a well-conditioned Jacobian."""
+    n, c = 256, 0.9
+    x = O.heq_picard(n, c, tol=1e-6)
+    J32 = O.heq_jacobian(x, c).astype(np.float32)
+    lu = O.HalfLU(O.round_half(J32), "fp16")
+    F = O.heq_residual(x, c)
+    b = (-F / np.linalg.norm(F)).astype(np.float32)
+    a = O.ir(J32, b, lu)
+    h = O.ir(J32, b, lu, scaled_half=True)
+    assert not a.failed and not h.failed
+    assert a.sweeps == h.sweeps
+    ref = np.linalg.solve(J32.astype(np.float64), b.astype(np.float64))
+    for res in (a, h):
+        assert np.linalg.norm(res.u - ref) <= 1e-5 * np.linalg.norm(ref)
