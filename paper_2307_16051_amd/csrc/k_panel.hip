@@ -472,6 +472,7 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
     __syncthreads();
 
     bool bad = false;
+    uint64_t pre[4][4];  // words requested ahead (see below)
     // L tile of leaf l: L^T = (U^{-1})^T X^T on waves 0..3 (fm: leaf columns,
     // fn: tile rows), from the published scaled U^{-1} halves.
     auto l21 = [&](int l) {
@@ -517,13 +518,17 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
     // Update of 32 columns (half hf) of block column b, both row halves of
     // the tile, by leaves l0 .. l1 - 1 at once: C^T -= sum_l U(l, b)^T L(r, l)^T
     // (one rounding), U(l, b) from leaf l's words.
-    auto upd_range = [&](int l0, int l1, int b, int hf) {
+    // use_pre: leaf l0's words are already issued into pre (tissue4)
+    auto upd_range = [&](int l0, int l1, int b, int hf, bool use_pre) {
         const int wofs = PUB_U12 + b * 2048 + op_word(hf, 0, h, l32, 0);
         constexpr int wstr = op_word(0, 1, 0, 0, 0);
         f32x16 acc[2] = {zero16(), zero16()};
         for (int l = l0; l < l1; ++l) {
             uint32_t uw[4][4];
-            tfetch4<4>(a.pub + (size_t)l * PUB_LEAF + wofs, wstr, a.tag0 + (uint32_t)l, uw, flags);
+            if (use_pre && l == l0)
+                twait4<4>(pre, a.pub + (size_t)l * PUB_LEAF + wofs, wstr, a.tag0 + (uint32_t)l, uw, flags);
+            else
+                tfetch4<4>(a.pub + (size_t)l * PUB_LEAF + wofs, wstr, a.tag0 + (uint32_t)l, uw, flags);
 #pragma unroll
             for (int fn = 0; fn < 2; ++fn) {
                 const int i = 32 * fn + l32;
@@ -556,7 +561,7 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
     };
     // the update by leaf l of block columns b0 .. b1, spread over the waves
     auto update = [&](int l, int b0, int b1) {
-        for (int u = w; u < 2 * (b1 - b0 + 1); u += 8) upd_range(l, l + 1, b0 + (u >> 1), u & 1);
+        for (int u = w; u < 2 * (b1 - b0 + 1); u += 8) upd_range(l, l + 1, b0 + (u >> 1), u & 1, false);
     };
 
     // ---- the leaves above this tile: L tile, then the rank-64 update of the
@@ -569,6 +574,14 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
         update(l, l + 1, l + 1 < r ? std::min(r + 1, nl - 1) : r);
         __syncthreads();
     }
+
+    // ---- the words of U(r - 1, r + 1), half w, that waves 0 and 1 apply to
+    // block r + 1 right after the inversion: requested now (leaf r - 1
+    // published them long ago) so that their latency is off the chain
+    const bool have_pre = r > 0 && r + 1 < nl && w < 2;
+    if (have_pre)
+        tissue4<4>(a.pub + (size_t)(r - 1) * PUB_LEAF + PUB_U12 + (r + 1) * 2048 + op_word(w, 0, h, l32, 0),
+                   op_word(0, 1, 0, 0, 0), pre);
 
     // ---- leaf r: factor the diagonal block (columns 64 r .. 64 r + 63) with
     // the partial-pivoting check.  Wave w keeps columns 8 w .. 8 w + 7 of all
@@ -594,8 +607,14 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
                     const float lx = x[kk] * rp;
                     const float lv = below ? lx : 0.0f;
                     x[kk] = below ? lx : x[kk];
+                    // all broadcasts first, then the updates: independent
+                    // readlanes issue back to back instead of alternating
+                    // with the FMAs that consume them
+                    float ub[8];
 #pragma unroll
-                    for (int c = kk + 1; c < 8; ++c) x[c] -= lv * lane_bcast(x[c], k);
+                    for (int c = kk + 1; c < 8; ++c) ub[c] = lane_bcast(x[c], k);
+#pragma unroll
+                    for (int c = kk + 1; c < 8; ++c) x[c] -= lv * ub[c];
                 }
 #pragma unroll
                 for (int c = 0; c < 8; ++c) Dm[lane][8 * p + c] = x[c];
@@ -606,9 +625,13 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
 #pragma unroll
                 for (int kk = 0; kk < 8; ++kk) lv[kk] = lane > 8 * p + kk ? Dm[lane][8 * p + kk] : 0.0f;
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk)
+                for (int kk = 0; kk < 8; ++kk) {
+                    float ub[8];
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) x[c] -= lv[kk] * lane_bcast(x[c], 8 * p + kk);
+                    for (int c = 0; c < 8; ++c) ub[c] = lane_bcast(x[c], 8 * p + kk);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) x[c] -= lv[kk] * ub[c];
+                }
             }
         }
         if (fail) sfail = 1;
@@ -749,9 +772,14 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
     // updates (block r + 1: leaf r - 1; later blocks: every leaf above) and
     // then forms and publishes their U rows: the next leaf's workgroup waits
     // only for block r + 1
-    for (int u = w; u < 2 * (nl - r - 1); u += 8) {
+    if (w < 2 * (nl - r - 1)) {  // the first unit apart: only it uses the words requested ahead
+        const int b = r + 1 + (w >> 1), hf = w & 1;
+        if (r > 0) upd_range(b == r + 1 ? r - 1 : 0, r, b, hf, have_pre);
+        u12(b, hf);
+    }
+    for (int u = w + 8; u < 2 * (nl - r - 1); u += 8) {
         const int b = r + 1 + (u >> 1), hf = u & 1;
-        if (r > 0) upd_range(b == r + 1 ? r - 1 : 0, r, b, hf);
+        if (r > 0) upd_range(0, r, b, hf, false);
         u12(b, hf);
     }
     __syncthreads();
