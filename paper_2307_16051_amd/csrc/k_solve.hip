@@ -107,23 +107,73 @@ struct lane_word {
                                              __HIP_MEMORY_SCOPE_AGENT)
                          : 0;
     }
+    // backoff: extra sleep between polls, in units of 256 cycles.  A block
+    // waiting for a tile far behind its own row block has time to spare, and
+    // every poll of the newest words competes with the poll of the block
+    // that needs them next, so far blocks poll rarely.
     __device__ __forceinline__ void settle(const uint64_t *t, int64_t idx, bool valid, uint32_t ep,
-                                           int *spins, int *flags)
+                                           int *spins, int *flags, int backoff = 0)
     {
         for (;;) {
+            if (ready(valid, ep)) return;
+            __builtin_amdgcn_s_sleep(1);
+            for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(4);
+            *spins += backoff > 0 ? backoff : 0;  // the bound counts sleeps, not polls
+            if (++*spins > SPIN_LIMIT) {
+                set_flag(&flags[FLAG_TIMEOUT], 1);
+                return;
+            }
             bool ok = true;
             if (valid) {
 #pragma unroll
                 for (int h = 0; h < tagged<V>::W; ++h) ok &= (uint32_t)(w[h] >> 32) == ep;
             }
-            if (__all(ok)) return;
-            __builtin_amdgcn_s_sleep(1);
-            if (++*spins > SPIN_LIMIT) {
-                set_flag(&flags[FLAG_TIMEOUT], 1);
-                return;
-            }
             if (!ok) issue(t, idx, valid);
         }
+    }
+    __device__ __forceinline__ bool ready(bool valid, uint32_t ep) const
+    {
+        bool ok = true;
+        if (valid) {
+#pragma unroll
+            for (int h = 0; h < tagged<V>::W; ++h) ok &= (uint32_t)(w[h] >> 32) == ep;
+        }
+        return __all(ok);
+    }
+    // The wait on the last hand-off before a block can finish.  settle()
+    // re-polls only after its previous poll has returned, so a value that
+    // lands just after a poll passed is seen almost two memory round trips
+    // later.  Here, once the first poll (*this, already issued) has missed,
+    // four polls are kept in flight, issued a quarter of a round trip apart:
+    // the value is seen about one trip after it lands.  Straight-line code (fully
+    // unrolled), so each check waits for its own poll only; after RING
+    // rounds it falls back to settle().
+    template <int RING>
+    __device__ __forceinline__ void settle_ring(const uint64_t *t, int64_t idx, bool valid,
+                                                uint32_t ep, int *spins, int *flags)
+    {
+        if (ready(valid, ep)) return;
+        issue(t, idx, valid);
+        lane_word b, c, d;
+        __builtin_amdgcn_s_sleep(9);
+        b.issue(t, idx, valid);
+        __builtin_amdgcn_s_sleep(9);
+        c.issue(t, idx, valid);
+        __builtin_amdgcn_s_sleep(9);
+        d.issue(t, idx, valid);
+#pragma unroll
+        for (int r = 0; r < RING; ++r) {
+            if (ready(valid, ep)) return;
+            issue(t, idx, valid);
+            if (b.ready(valid, ep)) { *this = b; return; }
+            b.issue(t, idx, valid);
+            if (c.ready(valid, ep)) { *this = c; return; }
+            c.issue(t, idx, valid);
+            if (d.ready(valid, ep)) { *this = d; return; }
+            d.issue(t, idx, valid);
+        }
+        *spins += 4 * RING;
+        settle(t, idx, valid, ep, spins, flags);
     }
     __device__ __forceinline__ V value() const
     {
@@ -290,7 +340,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
             load_tile_row<T, V, BS>(fvn, LU, lda, rowc, (int64_t)nj * BS, n);
             nxt.issue(tags, (int64_t)nj * BS + lane, true);
         }
-        cur.settle(tags, (int64_t)jb * BS + lane, true, epoch, &spins, flags);
+        cur.settle(tags, (int64_t)jb * BS + lane, true, epoch, &spins, flags, std::min(32, last - jb - 2));
         tile_fma<V, BS>(acc, fv, cur.value());
 #pragma unroll
         for (int c = 0; c < BS; ++c) fv[c] = fvn[c];
@@ -313,7 +363,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
             load_row<V, BS>(rr, Dr, lane);
             lane_word<V> xp;
             xp.issue(tags, (int64_t)last * BS + lane, true);
-            xp.settle(tags, (int64_t)last * BS + lane, true, epoch, &spins, flags);
+            xp.template settle_ring<8>(tags, (int64_t)last * BS + lane, true, epoch, &spins, flags);
             w -= row_times_lanes<V, BS>(rr, xp.value());
         }
         if (round_out) w = (V)to_f32((T)w);  // solution held in the factor precision
@@ -386,7 +436,7 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
             nxt.issue(tags, (int64_t)nj * BS + lane, true);
         }
         const bool valid = (int64_t)jb * BS + lane < n;
-        cur.settle(tags, (int64_t)jb * BS + lane, valid, epoch, &spins, flags);
+        cur.settle(tags, (int64_t)jb * BS + lane, valid, epoch, &spins, flags, std::min(32, jb - next - 2));
         tile_fma<V, BS>(acc, fv, valid ? cur.value() : (V)0);
 #pragma unroll
         for (int c = 0; c < BS; ++c) fv[c] = fvn[c];
@@ -404,7 +454,7 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
             const bool valid = (int64_t)next * BS + lane < n;
             lane_word<V> xn;
             xn.issue(tags, (int64_t)next * BS + lane, valid);
-            xn.settle(tags, (int64_t)next * BS + lane, valid, epoch, &spins, flags);
+            xn.template settle_ring<8>(tags, (int64_t)next * BS + lane, valid, epoch, &spins, flags);
             w -= row_times_lanes<V, BS>(rr, valid ? xn.value() : (V)0);
         }
         if (round_out) w = (V)to_f32((T)w);
