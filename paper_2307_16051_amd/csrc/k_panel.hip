@@ -677,61 +677,19 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
         su = scale_exp(m2.x);
         sl = scale_exp(m2.y);
     }
-    // ---- publish (U^{-1})^T (scaled halves; row j of the operand is column j
-    // of U^{-1}), and the same words to the side buffer
+    // ---- what leaf r passes on.  U(r, r + 1) first, since the next leaf's
+    // workgroup waits for it: waves 0 and 1 form it with the scaled halves of
+    // L^{-1} in registers, while waves 2..7 publish (U^{-1})^T (scaled
+    // halves; row j of the operand is column j of U^{-1}) and write the same
+    // words to the side buffer.  Then L^{-1} replaces Dm in LDS as the A
+    // operand of the remaining U row blocks.
     T *iv = (T *)a.inv + (size_t)r * IH_LEAF;
-    {
-        const uint32_t tag = a.tag0 + (uint32_t)r;
-        uint64_t *pr = a.pub + (size_t)r * PUB_LEAF;
-        const float fu = ldexpf(1.0f, su);
-        for (int e = t; e < 2048; e += TOP_THREADS) {
-            // e = op_word(fm, ks, h, l32, q)
-            const int q = e & 3, l32e = (e >> 2) & 31, he = (e >> 7) & 1, kse = (e >> 8) & 3, fme = e >> 10;
-            const int j = 32 * fme + l32e, k = 16 * kse + 8 * he + 2 * q;
-            const float v0 = k <= j ? Dm[k][j] * fu : 0.0f;
-            const float v1 = k + 1 <= j ? Dm[k + 1][j] * fu : 0.0f;
-            const T h0 = (T)v0, h1 = (T)v1;
-            const T q0 = (T)(v0 - to_f32(h0)), q1 = (T)(v1 - to_f32(h1));
-            tstore(pr + PUB_UINV + e, tag, pack2(h0, h1));
-            tstore(pr + PUB_UINV + 2048 + e, tag, pack2(q0, q1));
-            *(uint32_t *)(iv + IH_UHI + 2 * e) = pack2(h0, h1);
-            *(uint32_t *)(iv + IH_ULO + 2 * e) = pack2(q0, q1);
-        }
-        if (t < 4) tstore(pr + PUB_SCALE + t, tag, (uint32_t)su);
-    }
-    // ---- U rows of leaf r in block columns b > r: U12 = L^{-1} T_b.  Unit
-    // (b, fn): 32 columns of block b, both row halves.  A operand: the scaled
-    // halves of L^{-1} (rows 32 fm + l32); B operand: 8 consecutive tile rows
-    // of one column.
-    // The A operand (scaled halves of L^{-1}) goes to the side buffer and
-    // replaces Dm in LDS: wave w forms step ks = w & 3 of row half fm = w >> 2.
-    u32x4 *lop = (u32x4 *)Dm;  // [hi / lo][fm][ks][lane]
-    {
-        const float fl = ldexpf(1.0f, sl);
-        const int fm = w >> 2, ks = w & 3, m = 32 * fm + l32;
-        float v[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int k = 16 * ks + 8 * h + p;
-            v[p] = (k < m ? Dm[m][k] : (k == m ? 1.0f : 0.0f)) * fl;
-        }
-        vec hi, lo;
-        split8<T>(v, hi, lo);
-        const u32x4 uhv = __builtin_bit_cast(u32x4, hi), ulv = __builtin_bit_cast(u32x4, lo);
-        *(u32x4 *)(iv + IH_LHI + (w * 64 + lane) * 8) = uhv;
-        *(u32x4 *)(iv + IH_LLO + (w * 64 + lane) * 8) = ulv;
-        __syncthreads();  // every read of Dm done
-        lop[w * 64 + lane] = uhv;
-        lop[512 + w * 64 + lane] = ulv;
-        if (t == 0) {
-            int *ex = (int *)((T *)a.inv + IH_EXP);
-            ex[2 * r] = su;
-            ex[2 * r + 1] = sl;
-        }
-        __syncthreads();
-    }
     const float ful = ldexpf(1.0f, -sl);
-    auto u12 = [&](int b, int fn) {
+    // U rows of leaf r in block columns b > r: U12 = L^{-1} T_b.  Unit
+    // (b, fn): 32 columns of block b, both row halves.  A operand opa(fm, ks,
+    // lo): the high (lo = 0) or low part of L^{-1} (rows 32 fm + l32) scaled
+    // by 2^sl; B operand: 8 consecutive tile rows of one column.
+    auto u12 = [&](int b, int fn, auto opa) {
         const uint32_t tag = a.tag0 + (uint32_t)r;
         uint64_t *pw = a.pub + (size_t)r * PUB_LEAF + PUB_U12 + b * 2048;
         const int c = 64 * b + 32 * fn + l32;
@@ -749,8 +707,8 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
             f32x16 acc = zero16();
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
-                acc = pmma<T>::op(as_vec<T>(lop[(fm * 4 + ks) * 64 + lane]), tb[ks], acc);
-                acc = pmma<T>::op(as_vec<T>(lop[512 + (fm * 4 + ks) * 64 + lane]), tb[ks], acc);
+                acc = pmma<T>::op(opa(fm, ks, 0), tb[ks], acc);
+                acc = pmma<T>::op(opa(fm, ks, 1), tb[ks], acc);
             }
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
@@ -768,19 +726,73 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
             }
         }
     };
-    // block by block, each wave takes 32 columns through their remaining
-    // updates (block r + 1: leaf r - 1; later blocks: every leaf above) and
-    // then forms and publishes their U rows: the next leaf's workgroup waits
-    // only for block r + 1
-    if (w < 2 * (nl - r - 1)) {  // the first unit apart: only it uses the words requested ahead
-        const int b = r + 1 + (w >> 1), hf = w & 1;
-        if (r > 0) upd_range(b == r + 1 ? r - 1 : 0, r, b, hf, have_pre);
-        u12(b, hf);
+    // the scaled L^{-1} operand piece (fm, ks) of this lane, from Dm
+    auto linv8 = [&](int fm, int ks, vec &hi, vec &lo) {
+        const float fl = ldexpf(1.0f, sl);
+        const int m = 32 * fm + l32;
+        float v[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int k = 16 * ks + 8 * h + p;
+            v[p] = (k < m ? Dm[m][k] : (k == m ? 1.0f : 0.0f)) * fl;
+        }
+        split8<T>(v, hi, lo);
+    };
+    if (w < 2) {
+        if (r + 1 < nl) {
+            vec lah[2][4], lal[2][4];
+#pragma unroll
+            for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) linv8(fm, ks, lah[fm][ks], lal[fm][ks]);
+            if (r > 0) upd_range(r - 1, r, r + 1, w, have_pre);
+            u12(r + 1, w, [&](int fm, int ks, int lo) { return lo ? lal[fm][ks] : lah[fm][ks]; });
+        }
+    } else {
+        const uint32_t tag = a.tag0 + (uint32_t)r;
+        uint64_t *pr = a.pub + (size_t)r * PUB_LEAF;
+        const float fu = ldexpf(1.0f, su);
+        for (int e = t - 128; e < 2048; e += TOP_THREADS - 128) {
+            // e = op_word(fm, ks, h, l32, q)
+            const int q = e & 3, l32e = (e >> 2) & 31, he = (e >> 7) & 1, kse = (e >> 8) & 3, fme = e >> 10;
+            const int j = 32 * fme + l32e, k = 16 * kse + 8 * he + 2 * q;
+            const float v0 = k <= j ? Dm[k][j] * fu : 0.0f;
+            const float v1 = k + 1 <= j ? Dm[k + 1][j] * fu : 0.0f;
+            const T h0 = (T)v0, h1 = (T)v1;
+            const T q0 = (T)(v0 - to_f32(h0)), q1 = (T)(v1 - to_f32(h1));
+            tstore(pr + PUB_UINV + e, tag, pack2(h0, h1));
+            tstore(pr + PUB_UINV + 2048 + e, tag, pack2(q0, q1));
+            *(uint32_t *)(iv + IH_UHI + 2 * e) = pack2(h0, h1);
+            *(uint32_t *)(iv + IH_ULO + 2 * e) = pack2(q0, q1);
+        }
+        if (t - 128 < 4) tstore(pr + PUB_SCALE + (t - 128), tag, (uint32_t)su);
     }
-    for (int u = w + 8; u < 2 * (nl - r - 1); u += 8) {
+    // L^{-1} to the side buffer and into LDS in place of Dm: wave w forms
+    // step ks = w & 3 of row half fm = w >> 2
+    u32x4 *lop = (u32x4 *)Dm;  // [hi / lo][fm][ks][lane]
+    {
+        vec hi, lo;
+        linv8(w >> 2, w & 3, hi, lo);
+        const u32x4 uhv = __builtin_bit_cast(u32x4, hi), ulv = __builtin_bit_cast(u32x4, lo);
+        *(u32x4 *)(iv + IH_LHI + (w * 64 + lane) * 8) = uhv;
+        *(u32x4 *)(iv + IH_LLO + (w * 64 + lane) * 8) = ulv;
+        __syncthreads();  // every read of Dm done
+        lop[w * 64 + lane] = uhv;
+        lop[512 + w * 64 + lane] = ulv;
+        if (t == 0) {
+            int *ex = (int *)((T *)a.inv + IH_EXP);
+            ex[2 * r] = su;
+            ex[2 * r + 1] = sl;
+        }
+        __syncthreads();
+    }
+    // the remaining U row blocks, block by block, each wave 32 columns after
+    // their remaining updates (later blocks: every leaf above at once)
+    auto opl = [&](int fm, int ks, int lo) { return as_vec<T>(lop[lo * 512 + (fm * 4 + ks) * 64 + lane]); };
+    for (int u = w < 2 ? w + 8 : w; u < 2 * (nl - r - 1); u += 8) {
         const int b = r + 1 + (u >> 1), hf = u & 1;
         if (r > 0) upd_range(0, r, b, hf, false);
-        u12(b, hf);
+        u12(b, hf, opl);
     }
     __syncthreads();
 
