@@ -186,15 +186,6 @@ struct lane_word {
     }
 };
 
-// Row update with one published tile: acc += sum_c F[row][c0 + c] y[c0 + c].
-// fv holds the factor entries of this lane's row, yw lane c's published value.
-template <typename V, int BS>
-__device__ __forceinline__ void tile_fma(V &acc, const V (&fv)[BS], const V yv)
-{
-#pragma unroll
-    for (int c = 0; c < BS; ++c) acc += fv[c] * lane_bcast(yv, c);
-}
-
 template <typename T, typename V, int BS>
 __device__ __forceinline__ void load_tile_row(V (&fv)[BS], const T *__restrict__ LU, int64_t lda,
                                               int64_t rowc, int64_t c0, int64_t n)
@@ -223,22 +214,24 @@ template <typename V, int BS, bool LOWER>
 __device__ __forceinline__ void diag_inverse(const V *__restrict__ Dr, const V *__restrict__ rd,
                                              V *__restrict__ Di, int lane)
 {
+    // each row's sum in four interleaved partial sums, so the dependent
+    // chain is about a quarter as long
     V xi[BS];
     if constexpr (LOWER) {
 #pragma unroll
         for (int i = 0; i < BS; ++i) {
-            V v = lane == i ? (V)1 : (V)0;
+            V a[4] = {lane == i ? (V)1 : (V)0, 0, 0, 0};
 #pragma unroll
-            for (int k = 0; k < i; ++k) v -= Dr[i * BS + k] * xi[k];
-            xi[i] = v;
+            for (int k = 0; k < i; ++k) a[k & 3] -= Dr[i * BS + k] * xi[k];
+            xi[i] = (a[0] + a[1]) + (a[2] + a[3]);
         }
     } else {
 #pragma unroll
         for (int i = BS - 1; i >= 0; --i) {
-            V v = lane == i ? (V)1 : (V)0;
+            V a[4] = {lane == i ? (V)1 : (V)0, 0, 0, 0};
 #pragma unroll
-            for (int k = i + 1; k < BS; ++k) v -= Dr[i * BS + k] * xi[k];
-            xi[i] = v * rd[i];
+            for (int k = i + 1; k < BS; ++k) a[k & 3] -= Dr[i * BS + k] * xi[k];
+            xi[i] = ((a[0] + a[1]) + (a[2] + a[3])) * rd[i];
         }
     }
 #pragma unroll
@@ -274,6 +267,26 @@ __device__ __forceinline__ V row_times_lanes(const V (&r)[BS], V v)
     for (int c = 0; c < BS; ++c) a[c & 3] += r[c] * lane_bcast(v, c);
     return (a[0] + a[1]) + (a[2] + a[3]);
 }
+// The same product with v passed through LDS (vb: this wavefront's BS
+// entries): one store and BS/4 broadcast reads instead of BS readlanes,
+// which the compiler chains through one SGPR with a wait state each.
+// (Same sums in the same order as row_times_lanes, so the same result.)
+// vb must be 16-byte aligned.
+template <typename V, int BS>
+__device__ __forceinline__ V row_times_lds(const V (&r)[BS], V v, V *vb, int lane)
+{
+    constexpr int K = 16 / sizeof(V);
+    vb[lane] = v;  // one wavefront's LDS accesses complete in order
+    V a[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < BS; c += K) {
+        V u[K];
+        __builtin_memcpy(u, vb + c, 16);
+#pragma unroll
+        for (int k = 0; k < K; ++k) a[(c + k) & 3] += r[c + k] * u[k];
+    }
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
 // row `lane` of an LDS matrix with stride BS + 1, into registers
 template <typename V, int BS>
 __device__ __forceinline__ void load_row(V (&r)[BS], const V *__restrict__ R, int lane)
@@ -305,6 +318,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
     __shared__ __attribute__((aligned(16))) V Eb[BS * BS];        // L_{b,b-1}
     __shared__ V Di[BS * (BS + 1)];                               // D^{-1}
     __shared__ V part[4][BS];
+    __shared__ __attribute__((aligned(16))) V vb[4][BS];  // each wavefront's broadcast vector
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) s_blk = __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -341,7 +355,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
             nxt.issue(tags, (int64_t)nj * BS + lane, true);
         }
         cur.settle(tags, (int64_t)jb * BS + lane, true, epoch, &spins, flags, std::min(32, last - jb - 2));
-        tile_fma<V, BS>(acc, fv, cur.value());
+        acc += row_times_lds<V, BS>(fv, cur.value(), vb[wv], lane);
 #pragma unroll
         for (int c = 0; c < BS; ++c) fv[c] = fvn[c];
         cur = nxt;
@@ -356,7 +370,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
         }
         V rr[BS];
         load_row<V, BS>(rr, Di, lane);
-        V w = row_times_lanes<V, BS>(rr, z);
+        V w = row_times_lds<V, BS>(rr, z, vb[0], lane);
         if (blk > 0) {
             // the only work left after the predecessor publishes: one product
             // with a row already in registers
@@ -364,7 +378,7 @@ __global__ __launch_bounds__(256) void k_trsv_lower(int64_t n, const T *__restri
             lane_word<V> xp;
             xp.issue(tags, (int64_t)last * BS + lane, true);
             xp.template settle_ring<8>(tags, (int64_t)last * BS + lane, true, epoch, &spins, flags);
-            w -= row_times_lanes<V, BS>(rr, xp.value());
+            w -= row_times_lds<V, BS>(rr, xp.value(), vb[0], lane);
         }
         if (round_out) w = (V)to_f32((T)w);  // solution held in the factor precision
         if (rv) {
@@ -393,6 +407,7 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
     __shared__ V Di[BS * (BS + 1)];                               // D^{-1}
     __shared__ V rd[BS];
     __shared__ V part[4][BS];
+    __shared__ __attribute__((aligned(16))) V vb[4][BS];  // each wavefront's broadcast vector
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nb = (int)((n + BS - 1) / BS);
     if (tid == 0) s_blk = nb - 1 - __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -437,7 +452,7 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
         }
         const bool valid = (int64_t)jb * BS + lane < n;
         cur.settle(tags, (int64_t)jb * BS + lane, valid, epoch, &spins, flags, std::min(32, jb - next - 2));
-        tile_fma<V, BS>(acc, fv, valid ? cur.value() : (V)0);
+        acc += row_times_lds<V, BS>(fv, valid ? cur.value() : (V)0, vb[wv], lane);
 #pragma unroll
         for (int c = 0; c < BS; ++c) fv[c] = fvn[c];
         cur = nxt;
@@ -448,14 +463,14 @@ __global__ __launch_bounds__(256) void k_trsv_upper(int64_t n, const T *__restri
         const V z = rv ? yin[row] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) : (V)0;
         V rr[BS];
         load_row<V, BS>(rr, Di, lane);
-        V w = row_times_lanes<V, BS>(rr, z);
+        V w = row_times_lds<V, BS>(rr, z, vb[0], lane);
         if (has_next) {
             load_row<V, BS>(rr, Dr, lane);
             const bool valid = (int64_t)next * BS + lane < n;
             lane_word<V> xn;
             xn.issue(tags, (int64_t)next * BS + lane, valid);
             xn.template settle_ring<8>(tags, (int64_t)next * BS + lane, valid, epoch, &spins, flags);
-            w -= row_times_lanes<V, BS>(rr, valid ? xn.value() : (V)0);
+            w -= row_times_lds<V, BS>(rr, valid ? xn.value() : (V)0, vb[0], lane);
         }
         if (round_out) w = (V)to_f32((T)w);
         if (rv) {
