@@ -935,7 +935,10 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
     // FP16 column targets: column max in [256, 512), 2^7 headroom below 65504.
     // A factorisation that overflows is redone with targets 2^6 lower, and the
     // lower targets are kept for the rest of the solve (the Jacobian changes
-    // little from one Newton step to the next, so its growth does too).
+    // little from one Newton step to the next, so its growth does too).  The
+    // pivoting path starts at the lower targets: a matrix that needs row
+    // interchanges is not diagonally dominant, so its elimination can grow
+    // (a diagonally dominant one grows at most twofold and never pivots).
     float tl = 9.0f;
     // IR and GMRES-IR: b = -F/||F||, ||b||, u = 0 and r = b depend on F only,
     // so they are queued ahead of the Jacobian and the factorisation, and
@@ -958,6 +961,7 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
             CHK(tstop(&t_jac));
             CHK(tstart());
             auto refill = [&]() -> int {
+                if (want_scale && scaled && tl > 3.0f) tl -= 6.0f;
                 // the FP64 factorisation of a built-in problem takes the FP64
                 // Jacobian again (J holds only its FP32 rounding)
                 if ((w.prec == N3P_FP64 || w.mf) && p->kind != 2)
