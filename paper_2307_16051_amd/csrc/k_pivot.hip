@@ -20,15 +20,17 @@ namespace n3p {
 // leaf over rows [c0, Np), spread over P workgroups that each hold a
 // contiguous block of rows in registers (FP32 arithmetic, FP64 for FP64
 // storage).  Per column every workgroup reduces its own candidate and
-// publishes it -- row index, magnitude and the whole 64-value row -- as
-// tag-stamped 64-bit words (tag = global column + 1), written and polled with
-// agent-scope atomic accesses, so no cache-wide fence is needed.  Every
-// workgroup then reads all P candidates and takes the same decision from the
-// same words: no grid-wide barrier, one round trip for the candidates and one
-// for the winning row per column.  One wavefront per workgroup polls and
-// passes the result on through LDS.  Slots alternate with the column parity; a
-// workgroup publishes column k + 2 only after every workgroup has published
-// column k + 1, which each does only after it has finished reading column k.
+// publishes it as tag-stamped 64-bit words (tag = global column + 1), written
+// and polled with agent-scope atomic accesses, so no cache-wide fence is
+// needed: the row index and the candidate's values in the few columns the next
+// pivot depends on.  Every wavefront reads all P candidates and takes the same
+// decision from the same words -- no grid-wide barrier, and one round trip
+// per column, because the rank-1 update is split: columns k+1 and k+2 are
+// updated as soon as column k's pivot is known, the columns right of them one
+// column later, when column k's complete pivot row (published by its owner
+// while the next candidates travel) has arrived.  Per element the updates
+// still come in column order, so the factors are those of the unsplit
+// elimination.
 //
 // P <= PIVOT_MAX_WG workgroups of 256 threads, one row per thread (256 rows
 // per workgroup), fill one CU each on an otherwise idle device, so all are
@@ -75,37 +77,67 @@ template <> __device__ __forceinline__ double val_of<double>(const uint64_t *w)
     return __longlong_as_double((long long)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]));
 }
 
-// Poll NW consecutive words per lane (lanes with `have`) until every word of
-// the wavefront carries `tag`; bounded.
-template <int NW>
-__device__ __forceinline__ void poll_words(const uint64_t *p, bool have, uint32_t tag,
-                                           uint64_t (&w)[NW], bool &dead, int *flags)
-{
-    int spins = 0;
-    for (;;) {
-        bool ok = true;
-        if (have) {
-#pragma unroll
-            for (int h = 0; h < NW; ++h) {
-                w[h] = __hip_atomic_load(p + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok &= (uint32_t)(w[h] >> 32) == tag;
-            }
-        }
-        if (__all(ok) || dead) return;
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > PC_SPIN_LIMIT) {
-            set_flag(&flags[FLAG_TIMEOUT], 1);
-            dead = true;
-            return;
-        }
-    }
-}
-
 template <typename CT>
 __device__ __forceinline__ bool better(CT a, int ia, CT b, int ib)
 {
     return a > b || (a == b && ia < ib);
 }
+
+// Cross-lane moves within 16-lane rows (DPP), and lane reads into scalars.
+template <int CTRL> __device__ __forceinline__ int dpp_i(int x)
+{
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_v(float x)
+{
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(x)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_v(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_read(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_read(double x, int l)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, typename CT> __device__ __forceinline__ void amax_step(CT &a, int &i)
+{
+    const CT oa = dpp_v<CTRL>(a);
+    const int oi = dpp_i<CTRL>(i);
+    if (better(oa, oi, a, i)) { a = oa; i = oi; }
+}
+// The wavefront's largest a (ties to the lowest i), in every lane: pairs
+// within quads, half rows and rows by DPP, then the four rows' results.
+template <typename CT> __device__ __forceinline__ void wave_argmax(CT &a, int &i)
+{
+    amax_step<0xB1>(a, i);   // quad_perm [1,0,3,2]
+    amax_step<0x4E>(a, i);   // quad_perm [2,3,0,1]
+    amax_step<0x141>(a, i);  // row_half_mirror
+    amax_step<0x140>(a, i);  // row_mirror
+    CT b = lane_read(a, 0);
+    int j = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const CT rb = lane_read(a, 16 * r);
+        const int rj = __builtin_amdgcn_readlane(i, 16 * r);
+        if (better(rb, rj, b, j)) { b = rb; j = rj; }
+    }
+    a = b;
+    i = j;
+}
+
+// 16-byte LDS vectors of the compute type
+template <typename CT> struct cvec16;
+template <> struct cvec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct cvec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
 // 16-byte vectors of the storage types (row stores into LT)
 template <typename T> struct vec16;
@@ -115,69 +147,199 @@ template <> struct vec16<float> { typedef f32x4 type; };
 template <> struct vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
 // Exchange area (64-bit words, zeroed once per factorisation):
-//   cand [2][pmax][4]  : row index, magnitude (1 or 2 words)
-//   rows [2][pmax][64W]: the candidate rows, in register-slot order (every
-//                        workgroup is in the same column group when it reads)
-//   rowk [2][64W]      : row k before the interchange, slot order
+//   cand [2][pmax][PC_CW]  : per workgroup and column k: its candidate's row
+//                            index, then the candidate's values in columns
+//                            k-1, k, k+1, k+2 (W words each)
+//   ksm  [2][PC_CW]        : row k's values in columns k-1 .. k+3
+//   rows [PC_NS][pmax][64W]: the candidate rows, in column order
+//   rowk [PC_NS][64W]      : row k, in column order
 //   then int list[16][PC_LIST_INTS]: per leaf of the outer block, the count
 //   and the (dest, src) row pairs of its interchanges composed into one
 //   permutation.
-// State of one thread of the panel kernel; step<KK>(g) is column 8 g + KK.
+// Everything of column k is published together, in step k; the rows as they
+// stand then, still owing column k-1's update right of column k+1, which the
+// reader applies (one multiply-add per lane, the same operation the owner
+// would have done).  The small words are read in the round trip that decides
+// the pivot; a row is read ahead right after the decision and, if it had not
+// arrived, read again in step k + 1.  Slot reuse: small words are read in the
+// step that publishes them (2 slots); a row of column k is read by step
+// k + 1, and its slot is written again in step k + 3, which no workgroup
+// reaches before every workgroup has finished step k + 1 (3 slots).
+constexpr int PC_CW = 16;
+constexpr int PC_NS = 3;
+
+// State of one thread of the panel kernel (one row, position rowi of the
+// panel); step<KK>(g) is column k = 8 g + KK.  Entering step k, every row
+// below the finished ones holds columns k and k+1 updated through column k-1
+// and the columns right of them through column k-2: the update by column k-1
+// of those columns waits for column k-1's pivot row, which arrives in step k,
+// overlapped with the round trip that decides column k's pivot.
 template <typename T, typename CT>
 struct PcState {
-    static constexpr int R = pc_cfg<CT>::R, W = pc_cfg<CT>::W, TH = pc_cfg<CT>::TH, L = NB_LEAF;
+    static constexpr int W = pc_cfg<CT>::W, TH = pc_cfg<CT>::TH, L = NB_LEAF;
+    static_assert(pc_cfg<CT>::R == 1, "one row per thread");
     static constexpr int NWV = TH / 64;
-    static constexpr int RW = TH * R;  // rows per workgroup
+    static constexpr int RW = TH;  // rows per workgroup
     static constexpr int NONE = 0x7fffffff;
-    CT v[R][L];
-    int rowi[R];
+    typedef typename cvec16<CT>::type CV;
+    static constexpr int NE = 16 / sizeof(CT);
+    CT v[L];
+    int rowi;
     bool dead, nonfin;
     int tid, lane, wv, P, wg, m, pmax;
     int64_t c0;
-    uint64_t *cand, *rows, *rowk;
+    // the previous column: its pivot row, the workgroup that published it,
+    // the pivot value; the words of its complete pivot row and (at the
+    // wavefront holding position pp) of its row k, read ahead
+    int pp, ppw;
+    CT ppk, ppk2;  // pivot values of columns k-1 and k-2
+    uint64_t prw[W], pkw[W];
+    uint64_t *cand, *ksm, *rows, *rowk;
     int *flags;
     CT (*red_v)[NWV];
     int (*red_i)[NWV];
-    CT (*crow)[NWV][L];  // [parity][wavefront]: the wavefront's candidate row
-    CT (*krow_l)[L];     // [parity]: row k (workgroup 0)
-    CT (*prow_l)[L];     // [parity]: the pivot row, as read by wavefront 0
-    CT (*krow_x)[L];     // [parity]: row k, as read by wavefront 0 (workgroup holding p)
-    int *pl;             // [parity]: the pivot row index
+    CT (*csm)[NWV][4];  // [parity][wavefront]: its candidate's values, columns k-1 .. k+2
+    CT (*ksl)[8];       // [parity]: row k's values, columns k-1 .. k+3 (workgroup 0)
+    CT (*prow)[L];      // [wavefront]: the previous column's pivot row, complete
+    CT (*krw)[L];       // [wavefront]: the previous column's row k, complete
+    CT (*crow)[L];      // [wavefront]: a row being published
     int *pivs;
+
+    __device__ __forceinline__ bool holds(int pos) const
+    {
+        return pos / RW == wg && (pos % RW) / 64 == wv;
+    }
+
+    // complete the read-ahead words of one 64-value row (lane = column) of
+    // column kp: poll again until every word carries `tag`; then the update by
+    // column kp-1 its columns right of kp+1 were still owed when it was
+    // published (with the row's own multiplier and that column's pivot row,
+    // still in prow[wv]), into dst[lane]; bounded
+    __device__ __forceinline__ void finish_row(const uint64_t *src, uint32_t tag, uint64_t (&w)[W], CT *dst, int kp)
+    {
+        auto arrived = [&]() {
+            bool ok = true;
+#pragma unroll
+            for (int h = 0; h < W; ++h) ok &= (uint32_t)(w[h] >> 32) == tag;
+            return __all(ok) != 0;
+        };
+        // the first check outside the loop: it waits for these words alone,
+        // not for the stores issued after them
+        if (!arrived() && !dead) {
+            int spins = 0;
+            for (;;) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > PC_SPIN_LIMIT) {
+                    set_flag(&flags[FLAG_TIMEOUT], 1);
+                    dead = true;
+                    break;
+                }
+#pragma unroll
+                for (int h = 0; h < W; ++h) w[h] = __hip_atomic_load(src + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (arrived() || dead) break;
+            }
+        }
+        CT x = val_of<CT>(w);
+        if (kp >= 1 && ppk2 != (CT)0) {
+            const CT l = lane_read(x, kp - 1);
+            if (lane >= kp + 2) x = fma(-l, prow[wv][lane], x);
+        }
+        dst[lane] = x;
+    }
+    __device__ __forceinline__ const uint64_t *row_src(int kc, int q) const
+    {
+        return rows + ((size_t)((kc % PC_NS) * pmax + q) * L + lane) * W;
+    }
+    __device__ __forceinline__ const uint64_t *rowk_src(int kc) const
+    {
+        return rowk + ((size_t)(kc % PC_NS) * L + lane) * W;
+    }
+
+    // the thread at position pp takes the columns of row kp (complete, src in
+    // column order) that the interchange of column kp left to now: all but
+    // kp .. kp+3
+    __device__ __forceinline__ void take_row(const CT *src, int kp, int cb)
+    {
+#pragma unroll
+        for (int s0 = 0; s0 < L; s0 += NE) {
+            const CV x = *(const CV *)(src + ((s0 + cb) & (L - 1)));
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int c = (s0 + e + cb) & (L - 1);
+                v[s0 + e] = (c < kp || c >= kp + 4) ? x[e] : v[s0 + e];
+            }
+        }
+    }
+    // a row into LDS in column order (one lane)
+    __device__ __forceinline__ void stage_row(CT *dst, int cb) const
+    {
+#pragma unroll
+        for (int s0 = 0; s0 < L; s0 += NE) {
+            CV x;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) x[e] = v[s0 + e];
+            *(CV *)(dst + ((s0 + cb) & (L - 1))) = x;
+        }
+    }
+
+    // The interchange of column kp = k - 1 completed at position pp: the
+    // wavefront holding it reads row kp, and position pp takes the columns of
+    // it left to now (all but kp .. kp+3).  Before anything of step k.
+    __device__ __forceinline__ void complete_moved(int k, int cb)
+    {
+        const int kp = k - 1;
+        if (pp != kp && holds(pp)) {
+            finish_row(rowk_src(kp), (uint32_t)(c0 + kp + 1), pkw, krw[wv], kp);
+            if (rowi == pp) take_row(krw[wv], kp, cb);
+        }
+    }
+    // Column kp = k - 1's pivot row, complete, into prow[wv] (every
+    // wavefront); position kp takes it.
+    __device__ __forceinline__ void complete(int k, int cb)
+    {
+        const int kp = k - 1;
+        finish_row(row_src(kp, ppw), (uint32_t)(c0 + kp + 1), prw, prow[wv], kp);
+        if (rowi == kp) {
+#pragma unroll
+            for (int s0 = 0; s0 < L; s0 += NE) {
+                const CV x = *(const CV *)(prow[wv] + ((s0 + cb) & (L - 1)));
+#pragma unroll
+                for (int e = 0; e < NE; ++e) v[s0 + e] = x[e];
+            }
+        }
+    }
 
     template <int KK> __device__ __forceinline__ void step(int g)
     {
-        const int k = 8 * g + KK, lim = L - 8 * g;
+        const int k = 8 * g + KK, lim = L - 8 * g, cb = 8 * g;
         const int par = k & 1;
         const uint32_t tag = (uint32_t)(c0 + k + 1);
+        constexpr int SM = (KK + L - 1) % L, S0 = KK, S1 = KK + 1, S2 = KK + 2, S3 = KK + 3;
+        // the row column k-1 moved is completed first: it may be published now
+        // (as a candidate, or as row k)
+        if (k > 0) complete_moved(k, cb);
         // --- this workgroup's candidate
         CT best = (CT)-1;
         int bi = NONE;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (rowi[r] >= k && rowi[r] < m) {
-                CT a = fabs(v[r][KK]);
-                if (a != a) { nonfin = true; a = (CT)0; }
-                if (better(a, rowi[r], best, bi)) { best = a; bi = rowi[r]; }
-            }
+        if (rowi >= k && rowi < m) {
+            CT a = fabs(v[S0]);
+            if (a != a) { nonfin = true; a = (CT)0; }
+            best = a;
+            bi = rowi;
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const CT ob = __shfl_xor(best, off);
-            const int oi = __shfl_xor(bi, off);
-            if (better(ob, oi, best, bi)) { best = ob; bi = oi; }
+        wave_argmax(best, bi);
+        if (bi != NONE && rowi == bi) {
+            csm[par][wv][0] = v[SM];
+            csm[par][wv][1] = v[S0];
+            csm[par][wv][2] = v[S1];
+            csm[par][wv][3] = v[S2];
         }
-        // the wavefront's candidate row (and row k) staged in LDS by its owner,
-        // so that one wavefront publishes it with a single 64-lane store
-        if (bi != NONE && tid == (bi - wg * RW) % TH) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (r == (bi - wg * RW) / TH)
-#pragma unroll
-                    for (int s = 0; s < L; ++s) crow[par][wv][s] = v[r][s];
-        }
-        if (wg == 0 && tid == k) {
-#pragma unroll
-            for (int s = 0; s < L; ++s) krow_l[par][s] = v[0][s];
+        if (wg == 0 && rowi == k) {
+            ksl[par][0] = v[SM];
+            ksl[par][1] = v[S0];
+            ksl[par][2] = v[S1];
+            ksl[par][3] = v[S2];
+            ksl[par][4] = v[S3];
         }
         if (lane == 0) { red_v[par][wv] = best; red_i[par][wv] = bi; }
         __syncthreads();
@@ -187,57 +349,68 @@ struct PcState {
 #pragma unroll
         for (int w = 1; w < NWV; ++w)
             if (better(red_v[par][w], red_i[par][w], best, bi)) { best = red_v[par][w]; bi = red_i[par][w]; bwv = w; }
-        // --- publish: the candidate first, then its row; (workgroup 0) row k
-        if (wv == 0 && bi != NONE) {
-            if (lane == 0) {
-                uint64_t *cw = cand + ((size_t)par * pmax + wg) * 4;
-                put_word(cw, tag, (uint32_t)bi);
-                put_val(cw + 1, tag, best);
-            }
-            put_val(rows + ((size_t)par * pmax + wg) * L * W + lane * W, tag, crow[par][bwv][lane]);
+        // --- publish the small words: the candidate's, (workgroup 0) row k's
+        if (wv == 0 && bi != NONE && lane < 5) {
+            uint64_t *cw = cand + ((size_t)par * pmax + wg) * PC_CW;
+            if (lane == 0) put_word(cw, tag, (uint32_t)bi);
+            else put_val(cw + 1 + (lane - 1) * W, tag, csm[par][bwv][lane - 1]);
         }
-        if (wg == 0 && wv == NWV - 1) put_val(rowk + (size_t)par * L * W + lane * W, tag, krow_l[par][lane]);
-        // --- wavefront 0: the pivot row p from all P (<= 128) candidates, then
-        // the winning row and row k in one round trip; shared through LDS
-        if (wv == 0) {
-            int p = k;
-            CT cv = (CT)-1;
-            int ci = NONE;
+        if (wg == 0 && wv == NWV - 1 && lane < 5) put_val(ksm + (size_t)par * PC_CW + lane * W, tag, ksl[par][lane]);
+        // the candidate row (its wavefront) and row k (workgroup 0), complete
+        // but for column k-1's update of the columns right of k+1
+        if (wv == bwv && bi != NONE) {
+            if (rowi == bi) stage_row(crow[wv], cb);
+            put_val(rows + ((size_t)((k % PC_NS) * pmax + wg) * L + lane) * W, tag, crow[wv][lane]);
+        }
+        if (wg == 0 && wv == 0) {
+            if (rowi == k) stage_row(crow[0], cb);
+            put_val(rowk + ((size_t)(k % PC_NS) * L + lane) * W, tag, crow[0][lane]);
+        }
+
+        // --- while they travel: column k-1 completed, and its update of the
+        // columns right of k+1 (finished columns keep their values)
+        if (k > 0) {
+            complete(k, cb);
+            if (ppk != (CT)0 && rowi > k - 1 && rowi < m) {
+                const CT l = v[SM];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int q = lane + 64 * h;
-                if (h == 1 && P <= 64) break;
-                uint64_t cw[W + 1];
-                const bool have = q < P;
-                poll_words<W + 1>(cand + ((size_t)par * pmax + (have ? q : 0)) * 4, have, tag, cw, dead, flags);
-                if (have) {
-                    const int qi = (int)(uint32_t)cw[0];
-                    const CT qv = val_of<CT>(cw + 1);
-                    if (better(qv, qi, cv, ci)) { cv = qv; ci = qi; }
+                for (int s0 = (S2 / NE) * NE; s0 < L; s0 += NE) {
+                    const CV x = *(const CV *)(prow[wv] + ((s0 + cb) & (L - 1)));
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) {
+                        const int s = s0 + e;
+                        if (s >= S2) {
+                            const CT u = fma(-l, x[e], v[s]);
+                            v[s] = s < lim ? u : v[s];
+                        }
+                    }
                 }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const CT ob = __shfl_xor(cv, off);
-                const int oi = __shfl_xor(ci, off);
-                if (better(ob, oi, cv, ci)) { cv = ob; ci = oi; }
-            }
-            if (!dead && ci >= k && ci < m) p = ci;
-            const int pw = p / RW;  // workgroup holding row p
-            const bool need_k = p != k && pw == wg;
-            uint64_t w[2 * W];
-            const uint64_t *src = rows + ((size_t)par * pmax + pw) * L * W + lane * W;
-            const uint64_t *srck = rowk + (size_t)par * L * W + lane * W;
+        }
+
+        // --- every wavefront: the P candidates and row k's small words
+        uint64_t cw[2][1 + 4 * W] = {}, kw[5 * W];
+        {
             int spins = 0;
             for (;;) {
                 bool ok = true;
 #pragma unroll
-                for (int h = 0; h < W; ++h) {
-                    w[h] = __hip_atomic_load(src + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok &= (uint32_t)(w[h] >> 32) == tag;
-                    if (need_k) {
-                        w[W + h] = __hip_atomic_load(srck + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ok &= (uint32_t)(w[W + h] >> 32) == tag;
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int q = lane + 64 * hh;
+                    if (q < P) {
+#pragma unroll
+                        for (int h = 0; h < 1 + 4 * W; ++h) {
+                            cw[hh][h] = __hip_atomic_load(cand + ((size_t)par * pmax + q) * PC_CW + h,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ok &= (uint32_t)(cw[hh][h] >> 32) == tag;
+                        }
                     }
+                }
+#pragma unroll
+                for (int h = 0; h < 5 * W; ++h) {
+                    kw[h] = __hip_atomic_load(ksm + (size_t)par * PC_CW + h, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                    ok &= (uint32_t)(kw[h] >> 32) == tag;
                 }
                 if (__all(ok) || dead) break;
                 __builtin_amdgcn_s_sleep(1);
@@ -247,69 +420,77 @@ struct PcState {
                     break;
                 }
             }
-            prow_l[par][lane] = val_of<CT>(w);
-            if (need_k) krow_x[par][lane] = val_of<CT>(w + W);
-            if (lane == 0) pl[par] = p;
         }
-        __syncthreads();
-        const int p = pl[par];
-        const int pw = p / RW;
-        const bool holds_p = p != k && pw == wg && ((p - pw * RW) % TH) / 64 == wv;
+        CT cv = (CT)-1;
+        int ci = NONE;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            if (lane + 64 * hh < P) {
+                const int qi = (int)(uint32_t)cw[hh][0];
+                CT qv = fabs(val_of<CT>(cw[hh] + 1 + W));
+                if (qv != qv) qv = (CT)0;
+                if (better(qv, qi, cv, ci)) { cv = qv; ci = qi; }
+            }
+        }
+        wave_argmax(cv, ci);
+        const int p = (!dead && ci >= k && ci < m) ? ci : k;
+        const int pwg = p / RW;
+        // read ahead: the complete pivot row, and (holding position p) row k
+        const bool hold = p != k && holds(p);
+#pragma unroll
+        for (int h = 0; h < W; ++h) prw[h] = __hip_atomic_load(row_src(k, pwg) + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (hold)
+#pragma unroll
+            for (int h = 0; h < W; ++h) pkw[h] = __hip_atomic_load(rowk_src(k) + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the pivot row's values in columns k-1 .. k+2, from the lane that read them
+        CT pv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const CT a = val_of<CT>(cw[0] + 1 + j * W), b = val_of<CT>(cw[1] + 1 + j * W);
+            pv[j] = lane_read(pwg >= 64 ? b : a, pwg & 63);
+        }
+        const CT pk = pv[1];
+        CT pw1 = pv[2], pw2 = pv[3];
+        const bool fix = k > 0 && ppk != (CT)0;  // column k-1's update still owed
+        if (fix && k + 2 < L) pw2 = fma(-pv[0], prow[wv][k + 2], pw2);
         if (wg == 0 && tid == 0) pivs[k] = p;
-        // --- interchange rows k and p (only the wavefronts holding them)
-        if ((wg == 0 && wv == 0) || holds_p) {
-            bool isk[R], isp[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                isk[r] = rowi[r] == k;
-                isp[r] = holds_p && rowi[r] == p;
-            }
-#pragma unroll
-            for (int s = 0; s < L; ++s) {
-                const CT ps = prow_l[par][s];
-                const CT ks = holds_p ? krow_x[par][s] : (CT)0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (isk[r]) v[r][s] = ps;
-                    if (isp[r]) v[r][s] = ks;
-                }
-            }
-        }
-        // --- multipliers and the rank-1 update of the unfinished columns
-        const CT pk = prow_l[par][KK];
         if (pk == (CT)0 && wg == 0 && tid == 0) atomicCAS(&flags[FLAG_ZEROPIV], 0, (int)(c0 + k + 1));
-        bool upd[R];
-        CT l[R];
+        // --- the interchange: position p takes row k's columns k .. k+3 (the
+        // rest of row k follows in step k+1; position k takes the pivot row then)
+        if (p != k && rowi == p) {
+            CT r[5];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            upd[r] = pk != (CT)0 && rowi[r] > k && rowi[r] < m;
-            l[r] = upd[r] ? v[r][KK] / pk : (CT)0;
-            if (upd[r]) v[r][KK] = l[r];
+            for (int j = 0; j < 5; ++j) r[j] = val_of<CT>(kw + j * W);
+            if (fix && k + 2 < L) r[3] = fma(-r[0], prow[wv][k + 2], r[3]);
+            if (fix && k + 3 < L) r[4] = fma(-r[0], prow[wv][k + 3], r[4]);
+            v[S0] = r[1];
+            if (S1 < lim) v[S1] = r[2];
+            if (S2 < lim) v[S2] = r[3];
+            if (S3 < lim) v[S3] = r[4];
         }
-#pragma unroll
-        for (int s = KK + 1; s < L; ++s) {
-            if (s < lim) {
-                const CT ps = prow_l[par][s];
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (upd[r]) v[r][s] -= l[r] * ps;
-            }
+        // --- the multiplier, and the update of columns k+1 and k+2
+        if (pk != (CT)0 && rowi > k && rowi < m) {
+            const CT l = v[S0] / pk;
+            v[S0] = l;
+            if (S1 < lim) v[S1] = fma(-l, pw1, v[S1]);
+            if (S2 < lim) v[S2] = fma(-l, pw2, v[S2]);
         }
+        pp = p;
+        ppw = pwg;
+        ppk2 = ppk;
+        ppk = pk;
     }
 
     // rotate by 8 slots: the next group's columns move to slots 0..7
     __device__ __forceinline__ void rotate()
     {
+        CT t8[8];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            CT t8[8];
+        for (int q = 0; q < 8; ++q) t8[q] = v[q];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) t8[q] = v[r][q];
+        for (int s = 0; s < L - 8; ++s) v[s] = v[s + 8];
 #pragma unroll
-            for (int s = 0; s < L - 8; ++s) v[r][s] = v[r][s + 8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[r][L - 8 + q] = t8[q];
-        }
+        for (int q = 0; q < 8; ++q) v[L - 8 + q] = t8[q];
     }
 };
 
@@ -322,14 +503,14 @@ __global__ __launch_bounds__(pc_cfg<CT>::TH) void k_pivot_coop(int64_t Np, int64
                                                            int *__restrict__ flags)
 {
     typedef PcState<T, CT> S;
-    constexpr int R = S::R, W = S::W, L = NB_LEAF, RW = S::RW;
-    __shared__ CT red_v[2][S::NWV];
-    __shared__ int red_i[2][S::NWV];
-    __shared__ CT crow[2][S::NWV][L];
-    __shared__ CT krow_l[2][L];
-    __shared__ CT prow_l[2][L];
-    __shared__ CT krow_x[2][L];
-    __shared__ int pl[2];
+    constexpr int W = S::W, L = NB_LEAF, RW = S::RW, NWV = S::NWV;
+    __shared__ CT red_v[2][NWV];
+    __shared__ int red_i[2][NWV];
+    __shared__ CT csm[2][NWV][4];
+    __shared__ CT ksl[2][8];
+    __shared__ __attribute__((aligned(16))) CT prow[NWV][L];
+    __shared__ __attribute__((aligned(16))) CT krw[NWV][L];
+    __shared__ __attribute__((aligned(16))) CT crow[NWV][L];
     __shared__ int pivs[L];
     if (block_flag(&flags[FLAG_TIMEOUT])) return;
     S st;
@@ -341,33 +522,35 @@ __global__ __launch_bounds__(pc_cfg<CT>::TH) void k_pivot_coop(int64_t Np, int64
     st.m = (int)(Np - c0);
     st.pmax = pmax;
     st.c0 = c0;
+    st.pp = -1;
+    st.ppw = 0;
+    st.ppk = (CT)0;
+    st.ppk2 = (CT)0;
     st.cand = xch;
-    st.rows = xch + (size_t)8 * pmax;
-    st.rowk = st.rows + (size_t)2 * pmax * L * W;
+    st.ksm = xch + (size_t)2 * pmax * PC_CW;
+    st.rows = st.ksm + 2 * PC_CW;
+    st.rowk = st.rows + (size_t)PC_NS * pmax * L * W;
     st.flags = flags;
     st.red_v = red_v;
     st.red_i = red_i;
+    st.csm = csm;
+    st.ksl = ksl;
+    st.prow = prow;
+    st.krw = krw;
     st.crow = crow;
-    st.krow_l = krow_l;
-    st.prow_l = prow_l;
-    st.krow_x = krow_x;
-    st.pl = pl;
     st.pivs = pivs;
     st.dead = false;
     st.nonfin = false;
-    int *list = (int *)(st.rowk + 2 * L * W) + ((c0 - k0) / L) * PC_LIST_INTS;
+    int *list = (int *)(st.rowk + (size_t)PC_NS * L * W) + ((c0 - k0) / L) * PC_LIST_INTS;
     const int tid = st.tid, lane = st.lane, wv = st.wv, wg = st.wg, m = st.m;
 
+    st.rowi = wg * RW + tid;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        st.rowi[r] = wg * RW + r * S::TH + tid;
+    for (int j = 0; j < L; ++j) st.v[j] = (CT)0;
+    if (st.rowi < m) {
+        const T *src = A + (c0 + st.rowi) + c0 * lda;
 #pragma unroll
-        for (int j = 0; j < L; ++j) st.v[r][j] = (CT)0;
-        if (st.rowi[r] < m) {
-            const T *src = A + (c0 + st.rowi[r]) + c0 * lda;
-#pragma unroll
-            for (int j = 0; j < L; ++j) st.v[r][j] = (CT)to_f32(src[j * lda]);
-        }
+        for (int j = 0; j < L; ++j) st.v[j] = (CT)to_f32(src[j * lda]);
     }
 
     for (int g = 0; g < L / 8; ++g) {
@@ -381,24 +564,25 @@ __global__ __launch_bounds__(pc_cfg<CT>::TH) void k_pivot_coop(int64_t Np, int64
         st.template step<7>(g);
         st.rotate();
     }
+    // the last column's moved row and pivot row (slots back in column order)
+    st.complete_moved(L, 0);
+    st.complete(L, 0);
     if (st.nonfin) set_flag(&flags[FLAG_NONFINITE], 1);
 
     // --- the factored panel into A; rows below the leaf also into LT (K contiguous)
     typedef typename vec16<T>::type V16;
     constexpr int VE = 16 / sizeof(T);
     bool bad = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (st.rowi[r] >= m) continue;
-        T *dst = A + (c0 + st.rowi[r]) + c0 * lda;
-        T *lt = LT + (c0 + st.rowi[r]) * (int64_t)NB_OUT + (c0 - k0);
-        const bool below = st.rowi[r] >= L;
+    if (st.rowi < m) {
+        T *dst = A + (c0 + st.rowi) + c0 * lda;
+        T *lt = LT + (c0 + st.rowi) * (int64_t)NB_OUT + (c0 - k0);
+        const bool below = st.rowi >= L;
 #pragma unroll
         for (int q = 0; q < L / VE; ++q) {
             V16 pk16;
 #pragma unroll
             for (int e = 0; e < VE; ++e) {
-                const T x = to_store_d<T>((double)st.v[r][q * VE + e]);
+                const T x = to_store_d<T>((double)st.v[q * VE + e]);
                 bad |= !isfinite(to_f32(x));  // the stored value (FP16 overflows above 65504)
                 dst[(q * VE + e) * lda] = x;
                 pk16[e] = x;
@@ -610,7 +794,7 @@ static int64_t pc_pmax(int prec, int64_t Np)
 static int64_t pc_words(int prec, int64_t Np)
 {
     const int64_t pmax = pc_pmax(prec, Np), W = prec == N3P_FP64 ? 2 : 1;
-    return 8 * pmax + 2 * pmax * NB_LEAF * W + 2 * NB_LEAF * W;
+    return 2 * pmax * PC_CW + 2 * PC_CW + PC_NS * pmax * NB_LEAF * W + PC_NS * NB_LEAF * W;
 }
 
 size_t pivot_xch_bytes(int prec, int64_t Np)
