@@ -6,7 +6,8 @@
 // Per 64-column leaf: k_pivot_coop (pivot search, interchanges inside the
 // leaf, multipliers, ipiv) and k_gather_u12 (the leaf's interchanges on the
 // rest of its outer block, and its U row block there).  Per outer block:
-// k_gather_block (the block's interchanges on all other columns),
+// k_compose_lists and k_gather_block (the block's interchanges, composed into
+// one list, on all other columns),
 // k_lt_rebuild (the block's L transposed), k_u12 (U row blocks right of the
 // block).  The Schur-complement updates reuse the matrix-core GEMMs of
 // k_getrf.hip.
@@ -639,28 +640,91 @@ __global__ __launch_bounds__(pc_cfg<CT>::TH) void k_pivot_coop(int64_t Np, int64
     }
 }
 
-// Interchanges of an outer block's leaves (lists 0 .. nl-1, applied in order)
-// on the columns outside the block, [0, k0) and [kend, Np).  Two columns per
-// 256-thread workgroup, one row move per thread; every read of a list
-// completes before any write.
-template <typename T>
-__global__ __launch_bounds__(256) void k_gather_block(T *__restrict__ A, int64_t lda,
-                                                      const int *__restrict__ lists, int nl,
-                                                      int64_t k0, int64_t kend, int64_t ncol)
+// The interchange lists of an outer block's leaves (0 .. nl-1, applied in
+// order) composed into one list of (dest, src) row moves.  LDS holds, for each
+// row position >= k0, the offset of the row whose values end there; the lists
+// are applied to it in order (every read of a list before any write), and the
+// positions whose row changed make the list.  At most the block's rows and as
+// many rows from below change (each leaf moves at most 64 rows up).  One
+// workgroup; the order of the composed list is immaterial.
+constexpr int PC_CMAX = 2 * NB_OUT;
+constexpr int PC_COMP_INTS = 1 + 2 * PC_CMAX;
+__global__ __launch_bounds__(1024) void k_compose_lists(const int *__restrict__ lists, int nl, int64_t k0,
+                                                        int64_t Np, int *__restrict__ out)
 {
-    const int64_t q = (int64_t)blockIdx.x * 2 + (threadIdx.x >> 7);
-    const int e = threadIdx.x & 127;
-    const bool colok = q < ncol;
-    T *cp = A + (q < k0 ? q : q - k0 + kend) * lda;
+    __shared__ unsigned short src_of[PIVOT_MAX_NP];
+    __shared__ int cnt;
+    const int t = threadIdx.x;
+    const int n = (int)(Np - k0);
+    for (int i = t; i < n; i += 1024) src_of[i] = (unsigned short)i;
+    if (t == 0) cnt = 0;
+    __syncthreads();
     for (int l = 0; l < nl; ++l) {
         const int *list = lists + l * PC_LIST_INTS;
-        const bool act = colok && e < list[0];
-        T x = (T)0.0f;
-        if (act) x = cp[list[2 + 2 * e]];
+        const int c = list[0];
+        int d = 0;
+        unsigned short v = 0;
+        if (t < c) {
+            d = list[1 + 2 * t] - (int)k0;
+            v = src_of[list[2 + 2 * t] - (int)k0];
+        }
         __syncthreads();
-        if (act) cp[list[1 + 2 * e]] = x;
+        if (t < c) src_of[d] = v;
         __syncthreads();
     }
+    for (int i = t; i < n; i += 1024) {
+        if (src_of[i] != i) {
+            const int e = atomicAdd(&cnt, 1);
+            if (e < PC_CMAX) {
+                out[1 + 2 * e] = (int)k0 + i;
+                out[2 + 2 * e] = (int)k0 + src_of[i];
+            }
+        }
+    }
+    __syncthreads();
+    if (t == 0) out[0] = min(cnt, PC_CMAX);
+}
+
+// The composed interchanges of an outer block on the columns outside it,
+// [0, k0) and [kend, Np): four columns per 256-thread workgroup, every read
+// before any write.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_block(T *__restrict__ A, int64_t lda,
+                                                      const int *__restrict__ comp, int64_t k0,
+                                                      int64_t kend, int64_t ncol)
+{
+    constexpr int PER = PC_CMAX / 256, NC = 4;
+    const int t = threadIdx.x;
+    const int c = comp[0];
+    T *cp[NC];
+    bool colok[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const int64_t q = (int64_t)blockIdx.x * NC + j;
+        colok[j] = q < ncol;
+        cp[j] = A + (q < k0 ? q : q - k0 + kend) * lda;
+    }
+    int d[PER];
+    T x[PER][NC];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = t + 256 * i;
+        d[i] = -1;
+        if (e < c) {
+            d[i] = comp[1 + 2 * e];
+            const int sr = comp[2 + 2 * e];
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                if (colok[j]) x[i][j] = cp[j][sr];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        if (d[i] >= 0)
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                if (colok[j]) cp[j][d[i]] = x[i][j];
 }
 
 // Forward substitution of one column's 64 rows [c0, c0 + 64) with the unit
@@ -799,7 +863,7 @@ static int64_t pc_words(int prec, int64_t Np)
 
 size_t pivot_xch_bytes(int prec, int64_t Np)
 {
-    return (size_t)pc_words(prec, Np) * 8 + (size_t)PC_NLIST * PC_LIST_INTS * 4;
+    return (size_t)pc_words(prec, Np) * 8 + ((size_t)PC_NLIST * PC_LIST_INTS + PC_COMP_INTS) * 4;
 }
 
 static const int *pc_lists(int prec, int64_t Np, const void *xch)
@@ -859,14 +923,17 @@ hipError_t launch_gather_block(int prec, int64_t Np, int64_t k0, int64_t kend, v
 {
     const int64_t ncol = k0 + (Np - kend);
     const int nl = (int)((kend - k0) / NB_LEAF);
-    if (ncol <= 0 || nl <= 0 || nl > PC_NLIST) return nl > PC_NLIST ? hipErrorInvalidValue : hipSuccess;
+    if (nl > PC_NLIST || Np > PIVOT_MAX_NP) return hipErrorInvalidValue;
+    if (ncol <= 0 || nl <= 0) return hipSuccess;
     const int *lists = pc_lists(prec, Np, xch);
-    const unsigned grid = (unsigned)((ncol + 1) / 2);
+    int *comp = (int *)lists + PC_NLIST * PC_LIST_INTS;
+    hipLaunchKernelGGL(k_compose_lists, dim3(1), dim3(1024), 0, s, lists, nl, k0, Np, comp);
+    const unsigned grid = (unsigned)((ncol + 3) / 4);
     switch (prec) {
-    case N3P_FP16: hipLaunchKernelGGL(k_gather_block<f16>, dim3(grid), dim3(256), 0, s, (f16 *)A, lda, lists, nl, k0, kend, ncol); break;
-    case N3P_BF16: hipLaunchKernelGGL(k_gather_block<bf16>, dim3(grid), dim3(256), 0, s, (bf16 *)A, lda, lists, nl, k0, kend, ncol); break;
-    case N3P_FP32: hipLaunchKernelGGL(k_gather_block<float>, dim3(grid), dim3(256), 0, s, (float *)A, lda, lists, nl, k0, kend, ncol); break;
-    case N3P_FP64: hipLaunchKernelGGL(k_gather_block<double>, dim3(grid), dim3(256), 0, s, (double *)A, lda, lists, nl, k0, kend, ncol); break;
+    case N3P_FP16: hipLaunchKernelGGL(k_gather_block<f16>, dim3(grid), dim3(256), 0, s, (f16 *)A, lda, comp, k0, kend, ncol); break;
+    case N3P_BF16: hipLaunchKernelGGL(k_gather_block<bf16>, dim3(grid), dim3(256), 0, s, (bf16 *)A, lda, comp, k0, kend, ncol); break;
+    case N3P_FP32: hipLaunchKernelGGL(k_gather_block<float>, dim3(grid), dim3(256), 0, s, (float *)A, lda, comp, k0, kend, ncol); break;
+    case N3P_FP64: hipLaunchKernelGGL(k_gather_block<double>, dim3(grid), dim3(256), 0, s, (double *)A, lda, comp, k0, kend, ncol); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
