@@ -77,6 +77,13 @@ template <> __device__ __forceinline__ double val_of<double>(const uint64_t *w)
 {
     return __longlong_as_double((long long)(((uint64_t)(uint32_t)w[1] << 32) | (uint32_t)w[0]));
 }
+__device__ __forceinline__ void val_words(float v, uint32_t (&p)[1]) { p[0] = __float_as_uint(v); }
+__device__ __forceinline__ void val_words(double v, uint32_t (&p)[2])
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    p[0] = (uint32_t)b;
+    p[1] = (uint32_t)(b >> 32);
+}
 
 template <typename CT>
 __device__ __forceinline__ bool better(CT a, int ia, CT b, int ib)
@@ -149,11 +156,13 @@ template <> struct vec16<double> { typedef double type __attribute__((ext_vector
 
 // Exchange area (64-bit words, zeroed once per factorisation):
 //   cand [2][pmax][PC_CW]  : per workgroup and column k: its candidate's row
-//                            index, then the candidate's values in columns
-//                            k-1, k, k+1, k+2 (W words each)
+//                            index (W words, the first used), then the
+//                            candidate's values in columns k-1, k, k+1, k+2
+//                            (W words each)
 //   ksm  [2][PC_CW]        : row k's values in columns k-1 .. k+3
 //   rows [PC_NS][pmax][64W]: the candidate rows, in column order
 //   rowk [PC_NS][64W]      : row k, in column order
+//   dummy [pmax][4][64W]   : per wavefront, where its idle lanes' stores go
 //   then int list[16][PC_LIST_INTS]: per leaf of the outer block, the count
 //   and the (dest, src) row pairs of its interchanges composed into one
 //   permutation.
@@ -195,7 +204,7 @@ struct PcState {
     int pp, ppw;
     CT ppk, ppk2;  // pivot values of columns k-1 and k-2
     uint64_t prw[W], pkw[W];
-    uint64_t *cand, *ksm, *rows, *rowk;
+    uint64_t *cand, *ksm, *rows, *rowk, *dummy;
     int *flags;
     CT (*red_v)[NWV];
     int (*red_i)[NWV];
@@ -350,76 +359,105 @@ struct PcState {
 #pragma unroll
         for (int w = 1; w < NWV; ++w)
             if (better(red_v[par][w], red_i[par][w], best, bi)) { best = red_v[par][w]; bi = red_i[par][w]; bwv = w; }
-        // --- publish the small words: the candidate's, (workgroup 0) row k's
-        if (wv == 0 && bi != NONE && lane < 5) {
-            uint64_t *cw = cand + ((size_t)par * pmax + wg) * PC_CW;
-            if (lane == 0) put_word(cw, tag, (uint32_t)bi);
-            else put_val(cw + 1 + (lane - 1) * W, tag, csm[par][bwv][lane - 1]);
+        // --- publish.  Every wavefront issues the same stores every column
+        // (lanes with nothing to publish write a private dummy slot): the wait
+        // for a load issued before them then need not wait for them too (one
+        // wavefront's memory operations complete in order).
+        uint64_t *dmy = dummy + ((size_t)(wg * NWV + wv) * L + lane) * W;
+        {
+            // the candidate's small words (wavefront 0): row index, then its
+            // values in columns k-1 .. k+2
+            const bool real = wv == 0 && bi != NONE && lane < 5;
+            uint64_t *dst = real ? cand + ((size_t)par * pmax + wg) * PC_CW + lane * W : dmy;
+            uint32_t pw[W];
+            val_words(csm[par][bwv][(lane >= 1 && lane < 5) ? lane - 1 : 0], pw);
+            if (lane == 0) {
+                pw[0] = (uint32_t)bi;
+#pragma unroll
+                for (int h = 1; h < W; ++h) pw[h] = 0u;
+            }
+#pragma unroll
+            for (int h = 0; h < W; ++h) put_word(dst + h, tag, pw[h]);
         }
-        if (wg == 0 && wv == NWV - 1 && lane < 5) put_val(ksm + (size_t)par * PC_CW + lane * W, tag, ksl[par][lane]);
+        {
+            // row k's small words (workgroup 0)
+            const bool real = wg == 0 && wv == NWV - 1 && lane < 5;
+            put_val(real ? ksm + (size_t)par * PC_CW + lane * W : dmy, tag, ksl[par][lane < 5 ? lane : 4]);
+        }
         // the candidate row (its wavefront) and row k (workgroup 0), complete
         // but for column k-1's update of the columns right of k+1
-        if (wv == bwv && bi != NONE) {
-            if (rowi == bi) stage_row(crow[wv], cb);
-            put_val(rows + ((size_t)((k % PC_NS) * pmax + wg) * L + lane) * W, tag, crow[wv][lane]);
+        if (wv == bwv && bi != NONE && rowi == bi) stage_row(crow[wv], cb);
+        {
+            const bool real = wv == bwv && bi != NONE;
+            put_val(real ? rows + ((size_t)((k % PC_NS) * pmax + wg) * L + lane) * W : dmy, tag, crow[wv][lane]);
         }
-        if (wg == 0 && wv == 0) {
-            if (rowi == k) stage_row(crow[0], cb);
-            put_val(rowk + ((size_t)(k % PC_NS) * L + lane) * W, tag, crow[0][lane]);
+        if (wg == 0 && wv == 0 && rowi == k) stage_row(crow[0], cb);
+        {
+            const bool real = wg == 0 && wv == 0;
+            put_val(real ? rowk + ((size_t)(k % PC_NS) * L + lane) * W : dmy, tag, crow[wv][lane]);
         }
+
+        // --- every wavefront: the P candidates and row k's small words.  The
+        // first read is issued once column k-1 is completed, late enough for
+        // the other workgroups' words to have landed, and checked after
+        // column k-1's deferred update
+        uint64_t cw[2][5 * W] = {}, kw[5 * W];
+        auto read_small = [&]() {
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int q = lane + 64 * hh;
+                if (q < P)
+#pragma unroll
+                    for (int h = 0; h < 5 * W; ++h)
+                        cw[hh][h] = __hip_atomic_load(cand + ((size_t)par * pmax + q) * PC_CW + h,
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+#pragma unroll
+            for (int h = 0; h < 5 * W; ++h)
+                kw[h] = __hip_atomic_load(ksm + (size_t)par * PC_CW + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
+        auto arrived = [&]() {
+            bool ok = true;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+                if (lane + 64 * hh < P)
+#pragma unroll
+                    for (int h = 0; h < 5 * W; ++h) ok &= (uint32_t)(cw[hh][h] >> 32) == tag;
+#pragma unroll
+            for (int h = 0; h < 5 * W; ++h) ok &= (uint32_t)(kw[h] >> 32) == tag;
+            return __all(ok) != 0;
+        };
 
         // --- while they travel: column k-1 completed, and its update of the
         // columns right of k+1 (finished columns keep their values)
-        if (k > 0) {
-            complete(k, cb);
-            if (ppk != (CT)0 && rowi > k - 1 && rowi < m) {
-                const CT l = v[SM];
+        if (k > 0) complete(k, cb);
+        read_small();
+        if (k > 0 && ppk != (CT)0 && rowi > k - 1 && rowi < m) {
+            const CT l = v[SM];
 #pragma unroll
-                for (int s0 = (S2 / NE) * NE; s0 < L; s0 += NE) {
-                    const CV x = *(const CV *)(prow[wv] + ((s0 + cb) & (L - 1)));
+            for (int s0 = (S2 / NE) * NE; s0 < L; s0 += NE) {
+                const CV x = *(const CV *)(prow[wv] + ((s0 + cb) & (L - 1)));
 #pragma unroll
-                    for (int e = 0; e < NE; ++e) {
-                        const int s = s0 + e;
-                        if (s >= S2) {
-                            const CT u = fma(-l, x[e], v[s]);
-                            v[s] = s < lim ? u : v[s];
-                        }
+                for (int e = 0; e < NE; ++e) {
+                    const int s = s0 + e;
+                    if (s >= S2) {
+                        const CT u = fma(-l, x[e], v[s]);
+                        v[s] = s < lim ? u : v[s];
                     }
                 }
             }
         }
-
-        // --- every wavefront: the P candidates and row k's small words
-        uint64_t cw[2][1 + 4 * W] = {}, kw[5 * W];
-        {
+        if (!arrived() && !dead) {
             int spins = 0;
             for (;;) {
-                bool ok = true;
-#pragma unroll
-                for (int hh = 0; hh < 2; ++hh) {
-                    const int q = lane + 64 * hh;
-                    if (q < P) {
-#pragma unroll
-                        for (int h = 0; h < 1 + 4 * W; ++h) {
-                            cw[hh][h] = __hip_atomic_load(cand + ((size_t)par * pmax + q) * PC_CW + h,
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ok &= (uint32_t)(cw[hh][h] >> 32) == tag;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int h = 0; h < 5 * W; ++h) {
-                    kw[h] = __hip_atomic_load(ksm + (size_t)par * PC_CW + h, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                    ok &= (uint32_t)(kw[h] >> 32) == tag;
-                }
-                if (__all(ok) || dead) break;
                 __builtin_amdgcn_s_sleep(1);
                 if (++spins > PC_SPIN_LIMIT) {
                     set_flag(&flags[FLAG_TIMEOUT], 1);
                     dead = true;
                     break;
                 }
+                read_small();
+                if (arrived() || dead) break;
             }
         }
         CT cv = (CT)-1;
@@ -428,7 +466,7 @@ struct PcState {
         for (int hh = 0; hh < 2; ++hh) {
             if (lane + 64 * hh < P) {
                 const int qi = (int)(uint32_t)cw[hh][0];
-                CT qv = fabs(val_of<CT>(cw[hh] + 1 + W));
+                CT qv = fabs(val_of<CT>(cw[hh] + 2 * W));
                 if (qv != qv) qv = (CT)0;
                 if (better(qv, qi, cv, ci)) { cv = qv; ci = qi; }
             }
@@ -447,7 +485,7 @@ struct PcState {
         CT pv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const CT a = val_of<CT>(cw[0] + 1 + j * W), b = val_of<CT>(cw[1] + 1 + j * W);
+            const CT a = val_of<CT>(cw[0] + W + j * W), b = val_of<CT>(cw[1] + W + j * W);
             pv[j] = lane_read(pwg >= 64 ? b : a, pwg & 63);
         }
         const CT pk = pv[1];
@@ -531,6 +569,7 @@ __global__ __launch_bounds__(pc_cfg<CT>::TH) void k_pivot_coop(int64_t Np, int64
     st.ksm = xch + (size_t)2 * pmax * PC_CW;
     st.rows = st.ksm + 2 * PC_CW;
     st.rowk = st.rows + (size_t)PC_NS * pmax * L * W;
+    st.dummy = st.rowk + (size_t)PC_NS * L * W;
     st.flags = flags;
     st.red_v = red_v;
     st.red_i = red_i;
@@ -542,7 +581,7 @@ __global__ __launch_bounds__(pc_cfg<CT>::TH) void k_pivot_coop(int64_t Np, int64
     st.pivs = pivs;
     st.dead = false;
     st.nonfin = false;
-    int *list = (int *)(st.rowk + (size_t)PC_NS * L * W) + ((c0 - k0) / L) * PC_LIST_INTS;
+    int *list = (int *)(st.dummy + (size_t)pmax * NWV * L * W) + ((c0 - k0) / L) * PC_LIST_INTS;
     const int tid = st.tid, lane = st.lane, wv = st.wv, wg = st.wg, m = st.m;
 
     st.rowi = wg * RW + tid;
@@ -858,7 +897,9 @@ static int64_t pc_pmax(int prec, int64_t Np)
 static int64_t pc_words(int prec, int64_t Np)
 {
     const int64_t pmax = pc_pmax(prec, Np), W = prec == N3P_FP64 ? 2 : 1;
-    return 2 * pmax * PC_CW + 2 * PC_CW + PC_NS * pmax * NB_LEAF * W + PC_NS * NB_LEAF * W;
+    const int64_t nwv = pc_cfg<float>::TH / 64;
+    return 2 * pmax * PC_CW + 2 * PC_CW + PC_NS * pmax * NB_LEAF * W + PC_NS * NB_LEAF * W +
+           pmax * nwv * NB_LEAF * W;
 }
 
 size_t pivot_xch_bytes(int prec, int64_t Np)
