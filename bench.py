@@ -60,6 +60,12 @@ def parse():
     ap.add_argument("--precision-quick", action="store_true",
                     help="N=4096 H-equation and N=1024 dense only")
     ap.add_argument("--precision-md", default=None, help="also write the table as markdown here")
+    ap.add_argument("--dense-conds", default="100,10000,1000000",
+                    help="dense tanh workload: condition numbers (comma-separated)")
+    ap.add_argument("--dense-combos", default="FP16:IR,FP16:GMRES_IR,BF16:IR,BF16:GMRES_IR",
+                    help="dense tanh workload: prec:solver runs besides the FP64-LU reference")
+    ap.add_argument("--dense-no-fp64", action="store_true",
+                    help="dense tanh workload: skip the FP64-LU reference run")
     ap.add_argument("--reps", type=int, default=3, help="timed solves per precision run")
     return ap.parse_args()
 
@@ -197,7 +203,8 @@ def precision_bench(args):
         else:
             A, b, _ = dense_tanh_system_torch(n, cond, "cuda")
         its64 = None
-        for prec, solver in [("FP64", "DIRECT")] + [cs for cs in combos if cs[0] != "FP64"]:
+        ref = [] if args.dense_no_fp64 else [("FP64", "DIRECT")]
+        for prec, solver in ref + [cs for cs in combos if cs[0] != "FP64"]:
             opts = n3p.Options.default()
             ws = torch.empty(n3p.workspace_size(n, getattr(n3p, prec), getattr(n3p, solver), opts),
                              dtype=torch.uint8, device="cuda")
@@ -229,9 +236,9 @@ def precision_bench(args):
                               ("FP64", "DIRECT")])
     if args.precision_only in ("all", "dense"):
         dn = 1024 if args.precision_quick else 16384
-        for cond in (1e2, 1e4, 1e6):
-            dense(dn, cond, [("FP16", "IR"), ("FP16", "GMRES_IR"), ("BF16", "IR"),
-                             ("BF16", "GMRES_IR")])
+        combos = [tuple(cs.split(":")) for cs in args.dense_combos.split(",") if cs]
+        for cond in [float(c) for c in args.dense_conds.split(",") if c]:
+            dense(dn, cond, combos)
     if args.precision_md:
         write_precision_md(rows, args.precision_md, " ".join(["python bench.py"] + sys.argv[1:]))
 
