@@ -253,6 +253,63 @@ def test_getrf_fp64_pivoting_large_properties(env):
     assert R <= bound
 
 
+def pivot_pattern_matrix(kind, n, seed, eps):
+    """A permutation matrix plus noise of size eps.  "shift": ones on the
+    subdiagonal and in the corner, so column k's pivot is row k+1 and the row
+    moved down is row k+1's again at the next column (the row a column moves
+    is the next column's row k, every column).  "antidiag": ones on the
+    antidiagonal, so the pivots come from the far end of the panel."""
+    rng = np.random.default_rng(seed)
+    A = eps * rng.standard_normal((n, n))
+    if kind == "shift":
+        A[np.arange(1, n), np.arange(n - 1)] += 1.0
+        A[0, n - 1] += 1.0
+    else:
+        A[np.arange(n), np.arange(n)[::-1]] += 1.0
+    return A
+
+
+@pytest.mark.parametrize("kind", ["shift", "antidiag"])
+@pytest.mark.parametrize("n", [300, 1100])
+def test_getrf_fp64_pivot_patterns(env, kind, n):
+    """Structured interchanges against the oracle: same pivots, factors to the
+    order of the FP64 sums."""
+    n3p, torch = env
+    print("case getrf_fp64_pattern %s n=%d" % (kind, n), flush=True)
+    A = pivot_pattern_matrix(kind, n, 31 + n, 1e-3)
+    LU_ref, piv_ref, info_ref = O.getrf(A)
+    if kind == "shift":
+        assert np.array_equal(piv_ref[:-1], np.arange(1, n))  # the pattern holds
+    T = to_cm(torch, A, torch.float64)
+    ipiv, info = n3p.getrf(T)
+    assert info == info_ref == 0
+    assert np.array_equal(ipiv.cpu().numpy(), piv_ref)
+    np.testing.assert_allclose(from_cm(T), LU_ref, rtol=1e-12, atol=1e-12 * np.abs(LU_ref).max())
+
+
+@pytest.mark.parametrize("prec,u", [("fp16", U16), ("fp32", U32)])
+@pytest.mark.parametrize("kind", ["shift", "antidiag"])
+def test_getrf_low_precision_pivot_patterns(env, prec, u, kind):
+    """The same patterns in the low precisions: the pivots are clear-cut
+    (1 against noise of 1e-2), so they equal the oracle's, and the stored
+    factors meet the componentwise backward-error bound."""
+    n3p, torch = env
+    n = 600
+    print("case getrf_%s_pattern %s n=%d" % (prec, kind, n), flush=True)
+    dt = {"fp16": torch.float16, "fp32": torch.float32}[prec]
+    A = pivot_pattern_matrix(kind, n, 57, 1e-2)
+    T = to_cm(torch, A, dt)
+    A_in = from_cm(T)
+    _, piv_ref, _ = O.getrf(A_in)
+    ipiv, info = n3p.getrf(T)
+    assert info == 0
+    piv = ipiv.cpu().numpy()
+    assert np.array_equal(piv, piv_ref)
+    stages = (n + 511) // 512 + 8
+    eta_sub = {"fp16": 2.0 ** -25, "fp32": 2.0 ** -150}[prec]
+    check_backward_error(A_in, from_cm(T), piv, u, stages, U32, eta_sub)
+
+
 def test_getrf_tie_break_lowest_row(env):
     n3p, torch = env
     n = 96
