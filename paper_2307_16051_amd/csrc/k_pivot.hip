@@ -28,8 +28,8 @@ namespace n3p {
 // decision from the same words -- no grid-wide barrier, and one round trip
 // per column, because the rank-1 update is split: columns k+1 and k+2 are
 // updated as soon as column k's pivot is known, the columns right of them one
-// column later, when column k's complete pivot row (published by its owner
-// while the next candidates travel) has arrived.  Per element the updates
+// column later, when column k's pivot row (published with its candidate and
+// read ahead right after the decision) has arrived.  Per element the updates
 // still come in column order, so the factors are those of the unsplit
 // elimination.
 //
