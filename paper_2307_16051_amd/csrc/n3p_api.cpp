@@ -862,8 +862,10 @@ N3P_API int n3p_solve(const n3p_problem *p, double *x, int lu_prec, int ls,
         hipEvent_t a = nullptr, b = nullptr;
         ~EventPair()
         {
-            if (a) hipEventDestroy(a);
-            if (b) hipEventDestroy(b);
+            // nothing to report from a destructor: a failed destroy leaves the
+            // error to the next call that checks
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
         }
     } ev;
     HIPCHK(hipEventCreate(&ev.a));
