@@ -338,12 +338,13 @@ struct n3p_engine {
         }
     }
 
+    // releases only; a destructor has nobody to report a failure to
     ~n3p_engine()
     {
-        for (auto &kv : g_factor) hipGraphExecDestroy(kv.second);
-        if (g_sweep) hipGraphExecDestroy(g_sweep);
-        if (g_final) hipGraphExecDestroy(g_final);
-        if (s) hipStreamDestroy(s);
+        for (auto &kv : g_factor) (void)hipGraphExecDestroy(kv.second);
+        if (g_sweep) (void)hipGraphExecDestroy(g_sweep);
+        if (g_final) (void)hipGraphExecDestroy(g_final);
+        if (s) (void)hipStreamDestroy(s);
     }
 };
 
@@ -419,11 +420,14 @@ N3P_API int n3p_engine_create(n3p_engine **out, const n3p_engine_config *cfg,
         hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(ev, (hipStream_t)stream) != hipSuccess ||
         hipStreamWaitEvent(e->s, ev, 0) != hipSuccess) {
-        if (ev) hipEventDestroy(ev);
+        if (ev) (void)hipEventDestroy(ev);  // already failing: report the first error
         delete e;
         return N3P_E_HIP;
     }
-    hipEventDestroy(ev);
+    if (hipEventDestroy(ev) != hipSuccess) {
+        delete e;
+        return N3P_E_HIP;
+    }
     int st = 0;
     if (hipMemcpyAsync(e->d_desc, e->hdesc.data(), sizeof(BDesc) * c.max_slots,
                        hipMemcpyHostToDevice, e->s) != hipSuccess ||
@@ -442,9 +446,9 @@ N3P_API int n3p_engine_create(n3p_engine **out, const n3p_engine_config *cfg,
 N3P_API int n3p_engine_destroy(n3p_engine *e)
 {
     if (!e) return N3P_E_INVALID;
-    hipStreamSynchronize(e->s);
+    const hipError_t r = hipStreamSynchronize(e->s);
     delete e;
-    return 0;
+    return r == hipSuccess ? 0 : N3P_E_HIP;
 }
 
 N3P_API int n3p_engine_admit(n3p_engine *e, int64_t n, double c, int *slot)
@@ -545,11 +549,13 @@ N3P_API int n3p_engine_autotune(n3p_engine *e, n3p_engine_config *chosen, float 
                     best = e->cfg;
                 }
             }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
-    // graphs captured with the old grid sizes are stale
-    for (auto &kv : e->g_factor) hipGraphExecDestroy(kv.second);
+    bool ok = hipEventDestroy(a) == hipSuccess;
+    ok &= hipEventDestroy(b) == hipSuccess;
+    // graphs captured with the old grid sizes are stale: all are released
+    // (and forgotten) before any failure is reported
+    for (auto &kv : e->g_factor) ok &= hipGraphExecDestroy(kv.second) == hipSuccess;
     e->g_factor.clear();
+    if (!ok) return N3P_E_HIP;
     e->cfg = best;
     if (chosen) *chosen = best;
     if (n_candidates) *n_candidates = cand;
