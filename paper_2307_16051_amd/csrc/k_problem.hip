@@ -114,15 +114,18 @@ __device__ __forceinline__ float block_max_256(float v, float *sh)
 // costs one product instead of a division (the FP64 value may differ from
 // the division form in the last bits; its FP32 rounding stays within the
 // FP32 rounding bound of the exact entry).
-template <typename T>
-__device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np, double c,
-                                               const double *__restrict__ D,
-                                               const double *__restrict__ h,
-                                               float *__restrict__ J, int64_t ldj,
-                                               T *__restrict__ Ah, int64_t ldh,
-                                               float *__restrict__ colscale, float target_log2,
-                                               int *flags, float *sh,
-                                               const double *__restrict__ rowq = nullptr)
+// The column for one combination of the optional operands (HH: the Hankel
+// table h, RQ: the row factors rowq, HJ: J is written), so that the row loop
+// has no branch on them and its operand loads are issued several rows ahead.
+template <typename T, bool HH, bool RQ, bool HJ>
+__device__ __forceinline__ void heq_jac_column_m(int64_t j, int64_t n, int64_t Np, double c,
+                                                 const double *__restrict__ D,
+                                                 const double *__restrict__ h,
+                                                 float *__restrict__ J, int64_t ldj,
+                                                 T *__restrict__ Ah, int64_t ldh,
+                                                 float *__restrict__ colscale, float target_log2,
+                                                 int *flags, float *sh,
+                                                 const double *__restrict__ rowq)
 {
     const int t = threadIdx.x;
     T *col = Ah ? Ah + j * ldh : nullptr;
@@ -136,17 +139,22 @@ __device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np,
     float mx = 0.0f;
     bool bad = false;
     auto entry = [&](int64_t i) -> double {
-        const double hk = h ? h[i + j] : 1.0 / (double)(i + j + 1);
-        if (rowq) return (i == j ? 1.0 : 0.0) - rowq[i] * hk;
-        const double di = D[i];
-        const double kij = wgt * ((double)i + 0.5) * hk;
-        return (i == j ? 1.0 : 0.0) - kij / (di * di);
+        double hk;
+        if constexpr (HH) hk = h[i + j];
+        else hk = 1.0 / (double)(i + j + 1);
+        if constexpr (RQ) {
+            return (i == j ? 1.0 : 0.0) - rowq[i] * hk;
+        } else {
+            const double di = D[i];
+            const double kij = wgt * ((double)i + 0.5) * hk;
+            return (i == j ? 1.0 : 0.0) - kij / (di * di);
+        }
     };
+#pragma unroll 8
     for (int64_t i = t; i < n; i += 256) {
-        const double v = entry(i);
-        const float vf = (float)v;
-        if (J) J[i + j * ldj] = vf;
-        if (!isfinite(vf)) bad = true;
+        const float vf = (float)entry(i);
+        if constexpr (HJ) J[i + j * ldj] = vf;
+        bad |= !isfinite(vf);
         mx = fmaxf(mx, fabsf(vf));
     }
     if (bad && flags) set_flag(&flags[FLAG_NONFINITE], 1);
@@ -156,6 +164,7 @@ __device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np,
         s = col_scale_from_max(block_max_256(mx, sh), target_log2);
         if (t == 0) colscale[j] = s;
     }
+#pragma unroll 8
     for (int64_t i = t; i < n; i += 256) {
         // recompute in the same order so the FP32 value is identical to J's
         const double v = entry(i);
@@ -163,12 +172,36 @@ __device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np,
             col[i] = v;  // a double-precision factorisation takes the FP64 Jacobian itself
         } else {
             const T o = cvt_out<T>((float)v * s);
-            if (!isfinite((float)o)) bad = true;  // the stored value (FP16 range)
+            bad |= !isfinite((float)o);  // the stored value (FP16 range)
             col[i] = o;
         }
     }
     if (bad && flags) set_flag(&flags[FLAG_NONFINITE], 1);
     for (int64_t i = n + t; i < Np; i += 256) col[i] = cvt_out<T>(0.0f);
+}
+
+template <typename T>
+__device__ __forceinline__ void heq_jac_column(int64_t j, int64_t n, int64_t Np, double c,
+                                               const double *__restrict__ D,
+                                               const double *__restrict__ h,
+                                               float *__restrict__ J, int64_t ldj,
+                                               T *__restrict__ Ah, int64_t ldh,
+                                               float *__restrict__ colscale, float target_log2,
+                                               int *flags, float *sh,
+                                               const double *__restrict__ rowq = nullptr)
+{
+#define N3P_JAC(HH_, RQ_)                                                                            \
+    do {                                                                                             \
+        if (J) heq_jac_column_m<T, HH_, RQ_, true>(j, n, Np, c, D, h, J, ldj, Ah, ldh, colscale,     \
+                                                   target_log2, flags, sh, rowq);                    \
+        else heq_jac_column_m<T, HH_, RQ_, false>(j, n, Np, c, D, h, J, ldj, Ah, ldh, colscale,      \
+                                                  target_log2, flags, sh, rowq);                     \
+    } while (0)
+    if (h && rowq) N3P_JAC(true, true);
+    else if (h) N3P_JAC(true, false);
+    else if (rowq) N3P_JAC(false, true);
+    else N3P_JAC(false, false);
+#undef N3P_JAC
 }
 
 template <typename T>
@@ -184,6 +217,143 @@ __global__ __launch_bounds__(256) void k_heq_jac_round(int64_t n, int64_t Np, do
     __shared__ float sh[256];
     heq_jac_column<T>(blockIdx.x, n, Np, c, D, h, J, ldj, Ah, ldh, colscale, target_log2, flags, sh,
                       rowq);
+}
+
+// One-pass form for n <= JR_TH * JR_NPT: a column stays in registers between
+// its max reduction and its rounding, so every operand is read once (the
+// two-pass form reads the FP64 operands of every entry twice and is bound by
+// that cache traffic).  JR_NC columns per workgroup (they would share the row
+// factors; one column keeps the registers low enough for two workgroups per
+// CU, which measured faster).  Branch-free rows (clamped reads, masked
+// values), so the reads are issued ahead of their use.  Identical values.
+constexpr int JR_TH = 1024, JR_NPT = 16, JR_NC = 1;
+
+template <int NC>
+__device__ __forceinline__ void block_max_jr(float (&m)[NC], float (*sh)[JR_TH / 64])
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        float v = m[c];
+        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+        if (lane == 0) sh[c][w] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        float r = sh[c][0];
+#pragma unroll
+        for (int i = 1; i < JR_TH / 64; ++i) r = fmaxf(r, sh[c][i]);
+        m[c] = r;
+    }
+}
+
+template <typename T, bool HH, bool RQ, bool HJ>
+__global__ __launch_bounds__(JR_TH) void k_heq_jac_round1(int64_t n, int64_t Np, double c,
+                                                          const double *__restrict__ D,
+                                                          const double *__restrict__ h,
+                                                          float *__restrict__ J, int64_t ldj,
+                                                          T *__restrict__ Ah, int64_t ldh,
+                                                          float *__restrict__ colscale,
+                                                          float target_log2, int *flags,
+                                                          const double *__restrict__ rowq)
+{
+    __shared__ float sh[JR_NC][JR_TH / 64];
+    const int t = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * JR_NC;
+    const double wgt = c / (2.0 * (double)n);
+    float vf[JR_NC][JR_NPT], mx[JR_NC];
+    bool bad = false;
+#pragma unroll
+    for (int cc = 0; cc < JR_NC; ++cc) mx[cc] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < JR_NPT; ++q) {
+        const int64_t i = t + (int64_t)JR_TH * q;
+        const bool iin = i < n;
+        const int64_t ic = iin ? i : n - 1;  // clamped read, value masked below
+        double rq = 0.0, di = 1.0;
+        if constexpr (RQ) rq = rowq[ic];
+        else di = D[ic];
+#pragma unroll
+        for (int cc = 0; cc < JR_NC; ++cc) {
+            const int64_t j = j0 + cc;
+            const int64_t jc = j < n ? j : n - 1;
+            // the entry exactly as heq_jac_column forms it
+            double hk;
+            if constexpr (HH) hk = h[ic + jc];
+            else hk = 1.0 / (double)(ic + jc + 1);
+            double v;
+            if constexpr (RQ) {
+                v = (ic == jc ? 1.0 : 0.0) - rq * hk;
+            } else {
+                const double kij = wgt * ((double)ic + 0.5) * hk;
+                v = (ic == jc ? 1.0 : 0.0) - kij / (di * di);
+            }
+            const bool ok = iin && j < n;
+            const float x = ok ? (float)v : 0.0f;
+            if constexpr (HJ) {
+                if (ok) J[i + j * ldj] = x;
+            }
+            bad |= !isfinite(x);
+            mx[cc] = fmaxf(mx[cc], fabsf(x));
+            vf[cc][q] = x;
+        }
+    }
+    if (bad && flags) set_flag(&flags[FLAG_NONFINITE], 1);
+    if (!Ah) return;
+    block_max_jr<JR_NC>(mx, sh);
+    bool over = false;
+#pragma unroll
+    for (int cc = 0; cc < JR_NC; ++cc) {
+        const int64_t j = j0 + cc;
+        if (j >= Np) continue;
+        T *col = Ah + j * ldh;
+        if (j >= n) {  // padding column: e_j
+            for (int64_t i = t; i < Np; i += JR_TH) col[i] = cvt_out<T>(i == j ? 1.0f : 0.0f);
+            if (colscale && t == 0) colscale[j] = 1.0f;
+            continue;
+        }
+        const float sc = colscale ? col_scale_from_max(mx[cc], target_log2) : 1.0f;
+        if (colscale && t == 0) colscale[j] = sc;
+#pragma unroll
+        for (int q = 0; q < JR_NPT; ++q) {
+            const int64_t i = t + (int64_t)JR_TH * q;
+            const T o = cvt_out<T>(vf[cc][q] * sc);
+            if (i < n) {
+                over |= !isfinite((float)o);  // the stored value (FP16 range)
+                col[i] = o;
+            }
+        }
+        for (int64_t i = n + t; i < Np; i += JR_TH) col[i] = cvt_out<T>(0.0f);
+    }
+    if (over && flags) set_flag(&flags[FLAG_NONFINITE], 1);
+}
+
+template <typename T, bool HH, bool RQ>
+static void launch_jac1(int64_t n, int64_t Np, double c, const double *D, const double *h, float *J,
+                        int64_t ldj, T *Ah, int64_t ldh, float *colscale, float tl, int *flags,
+                        const double *rowq, hipStream_t s)
+{
+    const int64_t ncol = Ah ? Np : n;
+    const dim3 g((unsigned)((ncol + JR_NC - 1) / JR_NC)), b(JR_TH);
+    if (J)
+        hipLaunchKernelGGL((k_heq_jac_round1<T, HH, RQ, true>), g, b, 0, s, n, Np, c, D, h, J, ldj, Ah, ldh,
+                           colscale, tl, flags, rowq);
+    else
+        hipLaunchKernelGGL((k_heq_jac_round1<T, HH, RQ, false>), g, b, 0, s, n, Np, c, D, h, J, ldj, Ah, ldh,
+                           colscale, tl, flags, rowq);
+}
+
+// the one-pass form for any combination of the optional operands
+template <typename T>
+static void launch_jac_onepass(int64_t n, int64_t Np, double c, const double *D, const double *h, float *J,
+                               int64_t ldj, T *Ah, int64_t ldh, float *colscale, float tl, int *flags,
+                               const double *rowq, hipStream_t s)
+{
+    if (h && rowq) launch_jac1<T, true, true>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, rowq, s);
+    else if (h) launch_jac1<T, true, false>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, rowq, s);
+    else if (rowq) launch_jac1<T, false, true>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, rowq, s);
+    else launch_jac1<T, false, false>(n, Np, c, D, h, J, ldj, Ah, ldh, colscale, tl, flags, rowq, s);
 }
 
 // rowq[i] = (c/2N)(i + 1/2) / D_i^2 (the Jacobian's row factor)
@@ -665,6 +835,12 @@ static hipError_t heq_jac_round_t(int64_t n, int64_t Np, double c, const double 
 {
     if (rowq)
         hipLaunchKernelGGL(k_heq_rowq, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, c, D, rowq);
+    if constexpr (!std::is_same<T, double>::value) {
+        if (n <= (int64_t)JR_TH * JR_NPT) {
+            launch_jac_onepass<T>(n, Np, c, D, h, J, ldj, (T *)Ah, ldh, colscale, tl, flags, rowq, s);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL(k_heq_jac_round<T>, dim3((unsigned)(Ah ? Np : n)), dim3(256), 0, s, n, Np,
                        c, D, h, J, ldj, (T *)Ah, ldh, colscale, tl, flags, (const double *)rowq);
     return hipGetLastError();
