@@ -28,6 +28,27 @@ __global__ void k_hinv(int64_t m, double *h)
 // j = t, t + 256, ... in FP64; the block reduces in a fixed order.
 constexpr int HR = 16;
 
+// sum_j x_j h_{i+j} for rows i0 .. i0+HR-1 over this thread's columns, in
+// column order (HH: the Hankel table is given; FULL: every row is < n)
+template <bool HH, bool FULL>
+__device__ __forceinline__ void heq_residual_acc(int64_t i0, int64_t n, const double *__restrict__ x,
+                                                 const double *__restrict__ h, double (&acc)[HR])
+{
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const double xj = x[j];
+#pragma unroll
+        for (int r = 0; r < HR; ++r) {
+            const int64_t i = i0 + r;
+            if (FULL || i < n) {
+                double hk;
+                if constexpr (HH) hk = h[i + j];
+                else hk = 1.0 / (double)(i + j + 1);
+                acc[r] += xj * hk;
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void heq_residual_rows(int64_t i0, int64_t n, double c,
                                                   const double *__restrict__ x,
                                                   const double *__restrict__ h,
@@ -38,13 +59,15 @@ __device__ __forceinline__ void heq_residual_rows(int64_t i0, int64_t n, double 
     double acc[HR];
 #pragma unroll
     for (int r = 0; r < HR; ++r) acc[r] = 0.0;
-    for (int64_t j = t; j < n; j += 256) {
-        const double xj = x[j];
-#pragma unroll
-        for (int r = 0; r < HR; ++r) {
-            const int64_t i = i0 + r;
-            if (i < n) acc[r] += xj * (h ? h[i + j] : 1.0 / (double)(i + j + 1));
-        }
+    // the operand form and the row bound decided once, so the inner loop has
+    // no branch and its HR reads per column are issued together
+    const bool full = i0 + HR <= n;
+    if (h) {
+        if (full) heq_residual_acc<true, true>(i0, n, x, h, acc);
+        else heq_residual_acc<true, false>(i0, n, x, h, acc);
+    } else {
+        if (full) heq_residual_acc<false, true>(i0, n, x, h, acc);
+        else heq_residual_acc<false, false>(i0, n, x, h, acc);
     }
 #pragma unroll
     for (int r = 0; r < HR; ++r) red[r][t] = acc[r];
@@ -385,9 +408,10 @@ __global__ __launch_bounds__(256) void k_round_scale(int64_t n, int64_t Np, cons
     float s = 1.0f;
     float mx = 0.0f;
     bool bad = false;
-    for (int64_t i = t; i < n; i += 256) {
+#pragma unroll 8
+    for (int64_t i = t; i < n; i += 256) {  // branch-free, so the reads go out together
         const float v = src[i];
-        if (!isfinite(v)) bad = true;
+        bad |= !isfinite(v);
         mx = fmaxf(mx, fabsf(v));
     }
     if (bad && flags) set_flag(&flags[FLAG_NONFINITE], 1);
@@ -396,6 +420,7 @@ __global__ __launch_bounds__(256) void k_round_scale(int64_t n, int64_t Np, cons
         if (t == 0) colscale[j] = s;
     }
     bool over = false;
+#pragma unroll 8
     for (int64_t i = t; i < n; i += 256) {
         const T o = cvt_out<T>(src[i] * s);
         over |= !isfinite((double)o);  // the stored value (FP16 range)
