@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "n3p_internal.hpp"
@@ -240,20 +241,53 @@ int getrf_spec_top(const FactorWs &f, hipStream_t s)
 // row block right of the block (leaf by leaf: triangular solve, then rank-64
 // update of the block's later rows), and the K = NB_OUT update of the
 // trailing matrix.
+// The side stream of the pivoting path, one per device (default priority,
+// like every stream here).  A block's U rows and trailing update beyond the
+// next block's columns run on it, beside the next block's panel: the panel
+// holds at most 64 workgroups of the 256 CUs.
+static hipStream_t pivot_side_stream()
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)streams.size() <= dev) streams.resize((size_t)dev + 1, nullptr);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
+}
+
 int getrf_pivot(const FactorWs &f, hipStream_t s)
 {
     const int prec = f.prec;
     const int64_t Np = f.Np, lda = Np;
     const size_t es = elem_size(prec);
     char *A = (char *)f.A;
-    char *LT = (char *)f.LT;
     auto at = [&](int64_t i, int64_t j) { return (void *)(A + ((size_t)i + (size_t)j * lda) * es); };
-    auto lt = [&](int64_t row, int64_t col) { return (const void *)(LT + ((size_t)row * NB_OUT + (size_t)col) * es); };
+    // FP16/BF16: LT is double-buffered, so a block's update beyond the next
+    // block can still read its LT while the next block's panel writes the other
+    hipStream_t s2 = top_path(prec) ? pivot_side_stream() : nullptr;
+    char *LTb[2] = {(char *)f.LT, (char *)f.LT + (s2 ? (size_t)Np * NB_OUT * es : 0)};
+    struct Ev {
+        hipEvent_t e = nullptr;
+        ~Ev()
+        {
+            if (e) (void)hipEventDestroy(e);  // a destructor has nobody to report to
+        }
+    } ready, done;  // ready: a block's interchanges and LT formed; done: its side work
+    if (s2) {
+        HIPCHK(hipEventCreateWithFlags(&ready.e, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&done.e, hipEventDisableTiming));
+    }
+    bool side = false;  // side work queued that the main stream has not waited for
     HIPCHK(launch_pivot_reset(prec, Np, f.xch, s));
-    for (int64_t k0 = 0; k0 < Np; k0 += NB_OUT) {
+    for (int64_t blk = 0, k0 = 0; k0 < Np; ++blk, k0 += NB_OUT) {
         const int64_t kend = std::min<int64_t>(k0 + NB_OUT, Np);
+        char *LT = LTb[blk & 1];
+        auto lt = [&](int64_t row, int64_t col) { return (const void *)(LT + ((size_t)row * NB_OUT + (size_t)col) * es); };
         for (int64_t c0 = k0; c0 < kend; c0 += NB_LEAF) {
-            HIPCHK(launch_pivot_coop(prec, Np, c0, k0, f.A, lda, f.ipiv, f.LT, f.xch, f.flags, s));
+            HIPCHK(launch_pivot_coop(prec, Np, c0, k0, f.A, lda, f.ipiv, LT, f.xch, f.flags, s));
             HIPCHK(launch_gather_u12(prec, Np, c0, k0, kend, f.A, lda, f.xch, f.flags, s));
             const int64_t c1 = c0 + NB_LEAF;
             if (c1 < kend) {
@@ -261,21 +295,41 @@ int getrf_pivot(const FactorWs &f, hipStream_t s)
                                        at(c0, c1), lda, at(c1, c1), lda, f.flags, false, s));
             }
         }
+        // the block's interchanges reach the columns the side work updates
+        if (side) {
+            HIPCHK(hipStreamWaitEvent(s, done.e, 0));
+            side = false;
+        }
         HIPCHK(launch_gather_block(prec, Np, k0, kend, f.A, lda, f.xch, s));
         if (kend < Np) {
-            HIPCHK(launch_lt_rebuild(prec, Np, k0, k0, kend - k0, f.A, lda, f.LT, s));
-            for (int64_t c0 = k0; c0 < kend; c0 += NB_LEAF) {
-                const int64_t c1 = c0 + NB_LEAF;
-                HIPCHK(launch_u12(prec, c0, kend, Np, f.A, lda, f.flags, s));
-                if (c1 < kend)
-                    HIPCHK(launch_gemm_sub(prec, kend - c1, Np - kend, NB_LEAF, lt(c1, c0 - k0),
-                                           NB_OUT, at(c0, kend), lda, at(c1, kend), lda, f.flags,
-                                           false, s));
+            HIPCHK(launch_lt_rebuild(prec, Np, k0, k0, kend - k0, f.A, lda, LT, s));
+            // columns [kend, kn) here; with a side stream, [kn, Np) there
+            const int64_t kn = s2 ? std::min<int64_t>(kend + NB_OUT, Np) : Np;
+            if (kn < Np) {
+                HIPCHK(hipEventRecord(ready.e, s));
+                HIPCHK(hipStreamWaitEvent(s2, ready.e, 0));
             }
-            HIPCHK(launch_gemm_sub(prec, Np - kend, Np - kend, kend - k0, lt(kend, 0), NB_OUT,
-                                   at(k0, kend), lda, at(kend, kend), lda, f.flags, false, s));
+            auto u_rows_and_update = [&](int64_t j0, int64_t j1, hipStream_t st) -> int {
+                for (int64_t c0 = k0; c0 < kend; c0 += NB_LEAF) {
+                    const int64_t c1 = c0 + NB_LEAF;
+                    HIPCHK(launch_u12(prec, c0, j0, j1, f.A, lda, f.flags, st));
+                    if (c1 < kend)
+                        HIPCHK(launch_gemm_sub(prec, kend - c1, j1 - j0, NB_LEAF, lt(c1, c0 - k0), NB_OUT,
+                                               at(c0, j0), lda, at(c1, j0), lda, f.flags, false, st));
+                }
+                HIPCHK(launch_gemm_sub(prec, Np - kend, j1 - j0, kend - k0, lt(kend, 0), NB_OUT,
+                                       at(k0, j0), lda, at(kend, j0), lda, f.flags, false, st));
+                return 0;
+            };
+            CHK(u_rows_and_update(kend, kn, s));
+            if (kn < Np) {
+                CHK(u_rows_and_update(kn, Np, s2));
+                HIPCHK(hipEventRecord(done.e, s2));
+                side = true;
+            }
         }
     }
+    if (side) HIPCHK(hipStreamWaitEvent(s, done.e, 0));
     return 0;
 }
 
