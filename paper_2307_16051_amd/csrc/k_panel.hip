@@ -862,6 +862,11 @@ struct TopGemmArgs {
     int64_t ldb;
     void *C;
     int64_t ldc;
+    // a second region with the same K and leading dimensions (M2 = 0: none)
+    int M2, N2;
+    const void *At2;
+    const void *B2;
+    void *C2;
 };
 
 template <typename T>
@@ -874,11 +879,18 @@ __global__ __launch_bounds__(TOP_THREADS) void k_top_gemm(TopGemmArgs a)
         return;
     }
     if (block_flag(&a.top.flags[FLAG_FAIL])) return;
-    const int ntm = a.M / 256, ntn = a.N / 256;
-    int tm, tn;
-    grouped_tile(xcd_tile((int)blockIdx.x - a.ntop, ntm * ntn), ntm, ntn, tm, tn);
-    gemm16_tile<T, 256, 256, 2, 4, 32>(tm * 256, tn * 256, a.K, (const T *)a.At, a.ldat,
-                                       (const T *)a.B, a.ldb, (T *)a.C, a.ldc, a.top.flags, (T *)lds);
+    const int ntm = a.M / 256, ntn = a.N / 256, n1 = ntm * ntn;
+    const int ntm2 = a.M2 / 256, ntn2 = a.N2 / 256;
+    int tile = xcd_tile((int)blockIdx.x - a.ntop, n1 + ntm2 * ntn2), tm, tn;
+    if (tile < n1) {
+        grouped_tile(tile, ntm, ntn, tm, tn);
+        gemm16_tile<T, 256, 256, 2, 4, 32>(tm * 256, tn * 256, a.K, (const T *)a.At, a.ldat,
+                                           (const T *)a.B, a.ldb, (T *)a.C, a.ldc, a.top.flags, (T *)lds);
+    } else {
+        grouped_tile(tile - n1, ntm2, ntn2, tm, tn);
+        gemm16_tile<T, 256, 256, 2, 4, 32>(tm * 256, tn * 256, a.K, (const T *)a.At2, a.ldat,
+                                           (const T *)a.B2, a.ldb, (T *)a.C2, a.ldc, a.top.flags, (T *)lds);
+    }
 }
 
 // ====================================================================== k_trsm
@@ -1240,7 +1252,7 @@ hipError_t top_t(int64_t k0, int W, void *A, int64_t lda, void *LT, uint64_t *pu
 template <typename T>
 hipError_t top_gemm_t(TopGemmArgs a, hipStream_t s)
 {
-    const unsigned grid = (unsigned)(a.ntop + (a.M / 256) * (a.N / 256));
+    const unsigned grid = (unsigned)(a.ntop + (a.M / 256) * (a.N / 256) + (a.M2 / 256) * (a.N2 / 256));
     hipLaunchKernelGGL(k_top_gemm<T>, dim3(grid), dim3(TOP_THREADS), 0, s, a);
     return hipGetLastError();
 }
@@ -1273,12 +1285,15 @@ hipError_t launch_top(int prec, int64_t k0, int W, void *A, int64_t lda, void *L
 hipError_t launch_top_gemm(int prec, int64_t k0, int W, void *A, int64_t lda, void *LT,
                            uint64_t *pub, float *inv, int *flags, uint32_t tag0, int64_t M,
                            int64_t N, int64_t K, const void *At, int64_t ldat, const void *B,
-                           int64_t ldb, void *C, int64_t ldc, hipStream_t s)
+                           int64_t ldb, void *C, int64_t ldc, int64_t M2, int64_t N2,
+                           const void *At2, const void *B2, void *C2, hipStream_t s)
 {
     if (W < PT || W > NB_OUT || W % PT || lda % 8 || k0 % PT) return hipErrorInvalidValue;
     if (M <= 0 || N <= 0 || M % 256 || N % 256 || K % 32 || K <= 0) return hipErrorInvalidValue;
+    if (M2 < 0 || N2 < 0 || M2 % 256 || N2 % 256) return hipErrorInvalidValue;
+    if (M2 == 0 || N2 == 0) M2 = N2 = 0;
     TopGemmArgs g{TopArgs{k0, W, A, lda, LT, pub, inv, flags, tag0}, W / PT, (int)M, (int)N, (int)K,
-                  At, ldat, B, ldb, C, ldc};
+                  At, ldat, B, ldb, C, ldc, (int)M2, (int)N2, At2, B2, C2};
     switch (prec) {
     case N3P_FP16: return top_gemm_t<f16>(g, s);
     case N3P_BF16: return top_gemm_t<bf16>(g, s);

@@ -190,8 +190,8 @@ int getrf_spec(const FactorWs &f, hipStream_t s)
 // No-interchange attempt for FP16 / BF16 (verified against the
 // partial-pivoting rule), one outer block of up to NB_OUT columns at a time,
 // with look-ahead: block j's L below its square and U right of it (k_trsm),
-// the update of block j + 1's columns, then block j + 1's square factored
-// in the same launch as the rest of block j's update.  LT alternates between
+// the update of block j + 1's square, then that square factored in the same
+// launch as the rest of block j's update (the rows below the square included).  LT alternates between
 // two buffers by block parity.  Publication tags are unique within a
 // factorisation (the area is cleared once at its start).
 int getrf_spec_top(const FactorWs &f, hipStream_t s)
@@ -215,14 +215,17 @@ int getrf_spec_top(const FactorWs &f, hipStream_t s)
         const void *Lbelow = LTj + (size_t)kend * NB_OUT * es;
         HIPCHK(launch_trsm(prec, Np, k0, W, f.A, lda, LTj, f.inv, f.flags, s));
         const int W1 = (int)std::min<int64_t>(NB_OUT, Np - kend);
-        HIPCHK(launch_gemm_sub(prec, Np - kend, W1, W, Lbelow, NB_OUT, at(k0, kend), lda,
+        // the next square first; the rows below it join the fused update
+        HIPCHK(launch_gemm_sub(prec, W1, W1, W, Lbelow, NB_OUT, at(k0, kend), lda,
                                at(kend, kend), lda, f.flags, true, s));
         tag0 += NB_OUT / NB_LEAF;
         const int64_t rest = Np - kend - W1;
         if (rest > 0) {
             HIPCHK(launch_top_gemm(prec, kend, W1, f.A, lda, LTb[(j + 1) & 1], f.pub, f.inv, f.flags,
                                    tag0, Np - kend, rest, W, Lbelow, NB_OUT, at(k0, kend + W1),
-                                   lda, at(kend, kend + W1), lda, s));
+                                   lda, at(kend, kend + W1), lda, rest, W1,
+                                   (const char *)Lbelow + (size_t)W1 * NB_OUT * es, at(k0, kend),
+                                   at(kend + W1, kend), s));
         } else {
             HIPCHK(launch_top(prec, kend, W1, f.A, lda, LTb[(j + 1) & 1], f.pub, f.inv, f.flags,
                               tag0, s));

@@ -194,11 +194,14 @@ size_t top_inv_floats();
 hipError_t launch_top(int prec, int64_t k0, int W, void *A, int64_t lda, void *LT, uint64_t *pub,
                       float *inv, int *flags, uint32_t tag0, hipStream_t s);
 // the next block's square (k_top) fused with the rest of this block's
-// trailing update C[M x N] -= At^T B (256x256 tiles; M, N multiples of 256)
+// trailing update C[M x N] -= At^T B and C2[M2 x N2] -= At2^T B2 (256x256
+// tiles; M, N, M2, N2 multiples of 256; M2 = 0 for one region; same K, ldat,
+// ldb, ldc)
 hipError_t launch_top_gemm(int prec, int64_t k0, int W, void *A, int64_t lda, void *LT,
                            uint64_t *pub, float *inv, int *flags, uint32_t tag0, int64_t M,
                            int64_t N, int64_t K, const void *At, int64_t ldat, const void *B,
-                           int64_t ldb, void *C, int64_t ldc, hipStream_t s);
+                           int64_t ldb, void *C, int64_t ldc, int64_t M2, int64_t N2,
+                           const void *At2, const void *B2, void *C2, hipStream_t s);
 hipError_t launch_trsm(int prec, int64_t Np, int64_t k0, int W, void *A, int64_t lda, void *LT,
                        const float *inv, int *flags, hipStream_t s);
 // pivoting path: exchange area size (bytes), its reset, the cooperative leaf
