@@ -149,6 +149,29 @@ def test_getrf_low_precision_backward_error(env, prec, u, kind, n):
     check_backward_error(A_in, from_cm(T), piv, u, stages, U32, eta_sub)
 
 
+@pytest.mark.parametrize("prec,u", [("fp16", U16), ("bf16", UBF)])
+@pytest.mark.parametrize("n", [3100, 4100])
+def test_getrf_half_several_outer_blocks_backward_error(env, prec, u, n):
+    """The half-precision path over several 1024-column outer blocks: each
+    block's trailing update is split between the look-ahead (the next
+    diagonal square) and the launch that factors that square (the rest, the
+    rows below the square included), so every part of it is checked here
+    against the componentwise backward-error bound."""
+    n3p, torch = env
+    print("case getrf_%s_blocks n=%d" % (prec, n), flush=True)
+    dt = {"fp16": torch.float16, "bf16": torch.bfloat16}[prec]
+    A = O.heq_jacobian(np.ones(n), 0.99)
+    T = to_cm(torch, A, dt)
+    A_in = from_cm(T)
+    ipiv, info = n3p.getrf(T)
+    assert info == 0
+    piv = ipiv.cpu().numpy()
+    assert np.array_equal(piv, np.arange(n))
+    stages = (n + 511) // 512 + 8
+    eta_sub = {"fp16": 2.0 ** -25, "bf16": 2.0 ** -134}[prec]
+    check_backward_error(A_in, from_cm(T), piv, u, stages, U32, eta_sub)
+
+
 def subnormal_matrix(kind, n, seed):
     """Every entry an FP16 subnormal or zero (|a| < 2^-14).  "gaussian":
     independent entries (partial pivoting interchanges rows).  "banded": A =
