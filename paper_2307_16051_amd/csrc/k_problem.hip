@@ -272,7 +272,7 @@ __device__ __forceinline__ void block_max_jr(float (&m)[NC], float (*sh)[JR_TH /
 }
 
 template <typename T, bool HH, bool RQ, bool HJ>
-__global__ __launch_bounds__(JR_TH) void k_heq_jac_round1(int64_t n, int64_t Np, double c,
+__global__ __launch_bounds__(JR_TH, 8) void k_heq_jac_round1(int64_t n, int64_t Np, double c,
                                                           const double *__restrict__ D,
                                                           const double *__restrict__ h,
                                                           float *__restrict__ J, int64_t ldj,
