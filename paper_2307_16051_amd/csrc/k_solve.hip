@@ -600,6 +600,50 @@ __global__ __launch_bounds__(256) void k_gemv_f32_part(int64_t n, const float *_
     part[(int64_t)blockIdx.y * n + i] = (s0 + s1) + (s2 + s3);
 }
 
+// The same partial sums with four consecutive rows per thread (one 16-byte
+// load per column, so a wavefront reads 1 KB contiguous): needs n, lda and A
+// 16-byte aligned.  Per row the same four sums in the same order as above,
+// so the results are identical.
+constexpr int MV_ROWS4 = 1024;
+__global__ __launch_bounds__(256) void k_gemv_f32_part4(int64_t n, const float *__restrict__ A,
+                                                        int64_t lda, const float *__restrict__ u,
+                                                        double *__restrict__ part)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    __shared__ float ush[MV_CH];
+    const int64_t j0 = (int64_t)blockIdx.y * MV_CH;
+    const int64_t jn = std::min<int64_t>(MV_CH, n - j0);
+    if (threadIdx.x < jn) ush[threadIdx.x] = u[j0 + threadIdx.x];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * MV_ROWS4 + 4 * (int64_t)threadIdx.x;
+    if (i >= n) return;
+    const float *ap = A + i + j0 * lda;
+    double s[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[q][k] = 0.0;
+    int64_t c = 0;
+    for (; c + 4 <= jn; c += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const f4 a = *(const f4 *)(ap + (c + k) * lda);
+            const double uk = (double)ush[c + k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q][k] += (double)a[q] * uk;
+        }
+    }
+    for (; c < jn; ++c) {
+        const f4 a = *(const f4 *)(ap + c * lda);
+        const double uk = (double)ush[c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q][0] += (double)a[q] * uk;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        part[(int64_t)blockIdx.y * n + i + q] = (s[q][0] + s[q][1]) + (s[q][2] + s[q][3]);
+}
+
 __global__ void k_gemv_finish(int64_t n, int nch, const double *__restrict__ part,
                               const float *__restrict__ b, float *__restrict__ r)
 {
@@ -614,8 +658,12 @@ hipError_t launch_gemv_resid(int64_t n, const float *A, int64_t lda, const float
                              float *r, double *part, hipStream_t s)
 {
     const int nch = (int)((n + MV_CH - 1) / MV_CH);
-    hipLaunchKernelGGL(k_gemv_f32_part, dim3((unsigned)((n + MV_ROWS - 1) / MV_ROWS), nch),
-                       dim3(256), 0, s, n, A, lda, u, part);
+    if (n % 4 == 0 && lda % 4 == 0 && ((uintptr_t)A & 15) == 0)
+        hipLaunchKernelGGL(k_gemv_f32_part4, dim3((unsigned)((n + MV_ROWS4 - 1) / MV_ROWS4), nch),
+                           dim3(256), 0, s, n, A, lda, u, part);
+    else
+        hipLaunchKernelGGL(k_gemv_f32_part, dim3((unsigned)((n + MV_ROWS - 1) / MV_ROWS), nch),
+                           dim3(256), 0, s, n, A, lda, u, part);
     hipLaunchKernelGGL(k_gemv_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nch,
                        (const double *)part, b, r);
     return hipGetLastError();
