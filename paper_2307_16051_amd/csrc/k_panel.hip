@@ -226,31 +226,60 @@ template <typename T> __device__ __forceinline__ u32x4 to_u4(const uint32_t (&w)
     return v;
 }
 
-__device__ __forceinline__ float block_max(float v, float *red, int nw)
+// Max over a wavefront (every lane active) with DPP row operations: two quad
+// swaps, then the half-row and row mirrors leave each 16-lane row's max in
+// all of its lanes; the four rows are combined through lane reads.  (Max is
+// exact, so the order of the comparisons does not change the result.)
+__device__ __forceinline__ float dpp_f(float v, int ctrl_sel)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    const int b = __float_as_int(v);
+    int r;
+    switch (ctrl_sel) {
+    case 0: r = __builtin_amdgcn_update_dpp(b, b, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
+    case 1: r = __builtin_amdgcn_update_dpp(b, b, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
+    case 2: r = __builtin_amdgcn_update_dpp(b, b, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+    default: r = __builtin_amdgcn_update_dpp(b, b, 0x140, 0xF, 0xF, false); break; // row_mirror
+    }
+    return __int_as_float(r);
+}
+__device__ __forceinline__ float wave_max(float v)
+{
+    v = fmaxf(v, dpp_f(v, 0));
+    v = fmaxf(v, dpp_f(v, 1));
+    v = fmaxf(v, dpp_f(v, 2));
+    v = fmaxf(v, dpp_f(v, 3));
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return fmaxf(fmaxf(a, b), fmaxf(c, d));
+}
+
+// max over a block of NW wavefronts
+template <int NW>
+__device__ __forceinline__ float block_max(float v, float *red)
+{
+    v = wave_max(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     float m = red[0];
-    for (int i = 1; i < nw; ++i) m = fmaxf(m, red[i]);
+#pragma unroll
+    for (int i = 1; i < NW; ++i) m = fmaxf(m, red[i]);
     __syncthreads();
     return m;
 }
 
-
-// max over the block of two values at once (waves of 64 lanes)
+// max over a block of NW wavefronts of two values at once
+template <int NW>
 __device__ __forceinline__ float2 block_max2(float2 v, float2 *red)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        v.x = fmaxf(v.x, __shfl_xor(v.x, off));
-        v.y = fmaxf(v.y, __shfl_xor(v.y, off));
-    }
+    v.x = wave_max(v.x);
+    v.y = wave_max(v.y);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     float2 m = red[0];
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
         m.x = fmaxf(m.x, red[i].x);
         m.y = fmaxf(m.y, red[i].y);
     }
@@ -262,25 +291,37 @@ typedef float DmRow[PT + 1];
 
 // Inverses of the eight diagonal 8x8 blocks of U and of L, in place: wave J,
 // lanes 0..7 the columns of U_JJ^{-1} (back substitution), lanes 8..15 those
-// of L_JJ^{-1} (forward substitution, unit diagonal).
+// of L_JJ^{-1} (forward substitution, unit diagonal).  The block's entries
+// are read into registers first, so the reads issue together instead of one
+// per step of the dependent chain.
 __device__ __forceinline__ void inv_diag8(DmRow *Dm, int J, int lane)
 {
     const int c = lane & 7, b = 8 * J;
     float xd[8];
     if (lane < 8) {
+        float u[8][8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+            for (int m = rr; m < 8; ++m) u[rr][m] = Dm[b + rr][b + m];
 #pragma unroll
         for (int rr = 7; rr >= 0; --rr) {
             float v = rr == c ? 1.0f : 0.0f;
 #pragma unroll
-            for (int m = rr + 1; m < 8; ++m) v -= Dm[b + rr][b + m] * xd[m];
-            xd[rr] = v * rcp_nr(Dm[b + rr][b + rr]);
+            for (int m = rr + 1; m < 8; ++m) v -= u[rr][m] * xd[m];
+            xd[rr] = v * rcp_nr(u[rr][rr]);
         }
     } else if (lane < 16) {
+        float l[8][8];
+#pragma unroll
+        for (int rr = 1; rr < 8; ++rr)
+#pragma unroll
+            for (int m = 0; m < rr; ++m) l[rr][m] = Dm[b + rr][b + m];
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr) {
             float v = rr == c ? 1.0f : 0.0f;
 #pragma unroll
-            for (int m = 0; m < rr; ++m) v -= Dm[b + rr][b + m] * xd[m];
+            for (int m = 0; m < rr; ++m) v -= l[rr][m] * xd[m];
             xd[rr] = v;
         }
     }
@@ -301,19 +342,25 @@ __device__ __forceinline__ void inv_diag8(DmRow *Dm, int J, int lane)
 __device__ __forceinline__ void inv_double8(DmRow *Dm, float *Ts, int t)
 {
     const int tri = t >> 8, q = (t >> 6) & 3, i = (t >> 3) & 7, c = t & 7, p = 16 * q;
+    // each phase reads its 16 operands first, then sums in order
+    float ra[8], rb[8];
     float v = 0.0f;
     if (tri == 0) {  // T = U12 X22 (X22 upper)
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const float x = Dm[p + 8 + m][p + 8 + c];
-            v += Dm[p + i][p + 8 + m] * (m <= c ? x : 0.0f);
+            rb[m] = Dm[p + 8 + m][p + 8 + c];
+            ra[m] = Dm[p + i][p + 8 + m];
         }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v += ra[m] * (m <= c ? rb[m] : 0.0f);
     } else {         // T = L21 X11 (X11 unit lower)
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const float x = Dm[p + m][p + c];
-            v += Dm[p + 8 + i][p + m] * (m > c ? x : (m == c ? 1.0f : 0.0f));
+            rb[m] = Dm[p + m][p + c];
+            ra[m] = Dm[p + 8 + i][p + m];
         }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v += ra[m] * (m > c ? rb[m] : (m == c ? 1.0f : 0.0f));
     }
     Ts[t] = v;
     __syncthreads();
@@ -322,15 +369,19 @@ __device__ __forceinline__ void inv_double8(DmRow *Dm, float *Ts, int t)
     if (tri == 0) {  // X12 = -X11 T (X11 upper)
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const float x = Dm[p + i][p + m];
-            v += (m >= i ? x : 0.0f) * T[m * 8 + c];
+            ra[m] = Dm[p + i][p + m];
+            rb[m] = T[m * 8 + c];
         }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v += (m >= i ? ra[m] : 0.0f) * rb[m];
     } else {         // X21 = -X22 T (X22 unit lower)
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const float x = Dm[p + 8 + i][p + 8 + m];
-            v += (m < i ? x : (m == i ? 1.0f : 0.0f)) * T[m * 8 + c];
+            ra[m] = Dm[p + 8 + i][p + 8 + m];
+            rb[m] = T[m * 8 + c];
         }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v += (m < i ? ra[m] : (m == i ? 1.0f : 0.0f)) * rb[m];
     }
     __syncthreads();
     if (tri == 0) Dm[p + i][p + 8 + c] = -v;
@@ -349,9 +400,15 @@ __device__ __forceinline__ f32x4 mm16f32(FA fa, FB fb, int lane)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = 0.0f;
     const int ci = lane & 15, kq = lane >> 4;
+    // every operand read first, then the products in order
+    float av[KL / 4], bv[KL / 4];
 #pragma unroll
-    for (int kk = 0; kk < KL; kk += 4)
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa(ci, kk + kq), fb(kk + kq, ci), acc, 0, 0, 0);
+    for (int s = 0; s < KL / 4; ++s) {
+        av[s] = fa(ci, 4 * s + kq);
+        bv[s] = fb(4 * s + kq, ci);
+    }
+#pragma unroll
+    for (int s = 0; s < KL / 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
     return acc;
 }
 
@@ -667,13 +724,15 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
     int su, sl;
     {
         float mu = 0.0f, ml = 1.0f;
-        for (int e = t; e < PT * PT; e += TOP_THREADS) {
-            const int i = e >> 6, j = e & 63;
+        static_assert(PT * PT % TOP_THREADS == 0, "whole rounds");
+#pragma unroll
+        for (int k = 0; k < PT * PT / TOP_THREADS; ++k) {
+            const int e = t + k * TOP_THREADS, i = e >> 6, j = e & 63;
             const float v = fabsf(Dm[i][j]);
             if (i <= j) mu = fmaxf(mu, v);
             else ml = fmaxf(ml, v);
         }
-        float2 m2 = block_max2(make_float2(mu, ml), red2);
+        float2 m2 = block_max2<TOP_THREADS / 64>(make_float2(mu, ml), red2);
         su = scale_exp(m2.x);
         sl = scale_exp(m2.y);
     }
@@ -943,7 +1002,7 @@ __device__ __forceinline__ int stage_split(TrsmCtx<T> &c, const float (&y)[16], 
     float mx = 0.0f;
 #pragma unroll
     for (int q = 0; q < 16; ++q) mx = fmaxf(mx, fabsf(y[q]));
-    const int sy = scale_exp(block_max(c.w < 4 ? mx : 0.0f, c.red, 8));
+    const int sy = scale_exp(block_max<8>(c.w < 4 ? mx : 0.0f, c.red));
     const float fy = ldexpf(1.0f, sy);
     if (c.w >= 4) return sy;
 #pragma unroll
