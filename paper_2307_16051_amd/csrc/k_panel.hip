@@ -540,9 +540,16 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
         const int fm = w & 1, fn = (w >> 1) & 1, i = 32 * fn + l32;
         if (w < 4) {
             uint32_t uh[4][4], ul[4][4], se[1][4];
-            tfetch4<4>(pl + PUB_UINV + op_word(fm, 0, h, l32, 0), op_word(0, 1, 0, 0, 0), tag, uh, flags);
-            tfetch4<4>(pl + PUB_UINV + 2048 + op_word(fm, 0, h, l32, 0), op_word(0, 1, 0, 0, 0), tag, ul, flags);
-            tfetch4<1>(pl + PUB_SCALE, 0, tag, se, flags);
+            // all three requested before the first wait: one memory round
+            // trip once the leaf has published, not three
+            uint64_t vh[4][4], vl[4][4], vs[1][4];
+            const uint64_t *ph = pl + PUB_UINV + op_word(fm, 0, h, l32, 0);
+            tissue4<4>(ph, op_word(0, 1, 0, 0, 0), vh);
+            tissue4<4>(ph + 2048, op_word(0, 1, 0, 0, 0), vl);
+            tissue4<1>(pl + PUB_SCALE, 0, vs);
+            twait4<4>(vh, ph, op_word(0, 1, 0, 0, 0), tag, uh, flags);
+            twait4<4>(vl, ph + 2048, op_word(0, 1, 0, 0, 0), tag, ul, flags);
+            twait4<1>(vs, pl + PUB_SCALE, 0, tag, se, flags);
             sc = ldexpf(1.0f, -(int)se[0][0]);
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
@@ -632,13 +639,9 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
         __syncthreads();
     }
 
-    // ---- the words of U(r - 1, r + 1), half w, that waves 0 and 1 apply to
-    // block r + 1 right after the inversion: requested now (leaf r - 1
-    // published them long ago) so that their latency is off the chain
+    // the words of U(r - 1, r + 1), half w, that waves 0 and 1 apply to
+    // block r + 1 right after the inversion (requested before the inversion)
     const bool have_pre = r > 0 && r + 1 < nl && w < 2;
-    if (have_pre)
-        tissue4<4>(a.pub + (size_t)(r - 1) * PUB_LEAF + PUB_U12 + (r + 1) * 2048 + op_word(w, 0, h, l32, 0),
-                   op_word(0, 1, 0, 0, 0), pre);
 
     // ---- leaf r: factor the diagonal block (columns 64 r .. 64 r + 63) with
     // the partial-pivoting check.  Wave w keeps columns 8 w .. 8 w + 7 of all
@@ -715,6 +718,14 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
     // then three doublings (8 -> 16 -> 32 -> 64): for a pair of inverted
     // diagonal blocks X11, X22 and the block U12 (L21) between them,
     // X12 = -X11 (U12 X22) and X21 = -X22 (L21 X11).
+    // U(r - 1, r + 1) requested now: leaf r - 1 forms it after handing over
+    // U(r - 1, r), so a request before the diagonal factorisation could
+    // still find the words unpublished and the wait after the inversion
+    // would pay a whole round trip; requested here, the words are back with
+    // the right tag by then and their latency is off the chain
+    if (have_pre)
+        tissue4<4>(a.pub + (size_t)(r - 1) * PUB_LEAF + PUB_U12 + (r + 1) * 2048 + op_word(w, 0, h, l32, 0),
+                   op_word(0, 1, 0, 0, 0), pre);
     inv_diag8(Dm, w, lane);
     __syncthreads();
     inv_double8(Dm, Ts, t);
