@@ -587,12 +587,19 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
         const int wofs = PUB_U12 + b * 2048 + op_word(hf, 0, h, l32, 0);
         constexpr int wstr = op_word(0, 1, 0, 0, 0);
         f32x16 acc[2] = {zero16(), zero16()};
+        // the next leaf's words are requested before this leaf's products,
+        // so a run of leaves costs about one memory round trip each, not two
+        uint64_t vn[4][4];
+        if (!(use_pre && l1 > l0)) {
+            if (l0 < l1) tissue4<4>(a.pub + (size_t)l0 * PUB_LEAF + wofs, wstr, vn);
+        }
         for (int l = l0; l < l1; ++l) {
             uint32_t uw[4][4];
             if (use_pre && l == l0)
                 twait4<4>(pre, a.pub + (size_t)l * PUB_LEAF + wofs, wstr, a.tag0 + (uint32_t)l, uw, flags);
             else
-                tfetch4<4>(a.pub + (size_t)l * PUB_LEAF + wofs, wstr, a.tag0 + (uint32_t)l, uw, flags);
+                twait4<4>(vn, a.pub + (size_t)l * PUB_LEAF + wofs, wstr, a.tag0 + (uint32_t)l, uw, flags);
+            if (l + 1 < l1) tissue4<4>(a.pub + (size_t)(l + 1) * PUB_LEAF + wofs, wstr, vn);
 #pragma unroll
             for (int fn = 0; fn < 2; ++fn) {
                 const int i = 32 * fn + l32;
