@@ -808,10 +808,14 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
         const float fl = ldexpf(1.0f, sl);
         const int m = 32 * fm + l32;
         float v[8];
+        // every entry read (the address is always in the block), then the
+        // triangle selected, so the reads are not masked one by one
+#pragma unroll
+        for (int p = 0; p < 8; ++p) v[p] = Dm[m][16 * ks + 8 * h + p];
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             const int k = 16 * ks + 8 * h + p;
-            v[p] = (k < m ? Dm[m][k] : (k == m ? 1.0f : 0.0f)) * fl;
+            v[p] = (k < m ? v[p] : (k == m ? 1.0f : 0.0f)) * fl;
         }
         split8<T>(v, hi, lo);
     };
