@@ -630,9 +630,39 @@ __device__ __forceinline__ void top_body(const TopArgs &a, int r, char *lds)
             }
         }
     };
+    // upd_range for one leaf and one row half fn of the tile (the same sums
+    // in the same order), so that four waves share a block
+    auto upd_half = [&](int l, int b, int hf, int fn) {
+        uint32_t uw[4][4];
+        tfetch4<4>(a.pub + (size_t)l * PUB_LEAF + PUB_U12 + b * 2048 + op_word(hf, 0, h, l32, 0),
+                   op_word(0, 1, 0, 0, 0), a.tag0 + (uint32_t)l, uw, flags);
+        const int i = 32 * fn + l32;
+        f32x16 acc = zero16();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const vec lb = as_vec<T>(*(const u32x4 *)&tile[tix(i, 64 * l + 16 * ks + 8 * h, W)]);
+            acc = pmma<T>::op(as_vec<T>(to_u4<T>(uw[ks])), lb, acc);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            u32x2 *p = (u32x2 *)&tile[tix(i, 64 * b + 32 * hf + 8 * g + 4 * h, W)];
+            const u32x2 cv = *p;
+            T o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                o[q] = (T)(to_f32(from_bits<T>(cv[q >> 1] >> (16 * (q & 1)))) - acc[4 * g + q]);
+                bad |= !isfinite(to_f32(o[q]));
+            }
+            u32x2 st;
+            st[0] = pack2(o[0], o[1]);
+            st[1] = pack2(o[2], o[3]);
+            *p = st;
+        }
+    };
     // the update by leaf l of block columns b0 .. b1, spread over the waves
+    // (four units per block: column half hf, row half fn)
     auto update = [&](int l, int b0, int b1) {
-        for (int u = w; u < 2 * (b1 - b0 + 1); u += 8) upd_range(l, l + 1, b0 + (u >> 1), u & 1, false);
+        for (int u = w; u < 4 * (b1 - b0 + 1); u += 8) upd_half(l, b0 + (u >> 2), (u >> 1) & 1, u & 1);
     };
 
     // ---- the leaves above this tile: L tile, then the rank-64 update of the
